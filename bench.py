@@ -1,0 +1,322 @@
+"""Benchmark of the HJ-reachability safe-set solve on one MI355X.
+
+Default workload (one "step"): the initial safe-set computation of the
+near-hover quadcopter decomposed into its x, y (4-D, 41^4) and z (2-D, 101^2)
+subsystems, FP32, disturbance bound 0.5, each subsystem solved coarse-to-fine
+(21^4 -> 41^4, 51^2 -> 101^2) from a cold start, all three in one batched
+device solve.  Every step runs the whole path: level set-up, initialisation,
+both RK stages, the residual reduction and stop test, the level transition
+and the decomposed batch.
+
+Metric: grid cell-updates per second (nodes x RK2 steps, summed over levels
+and subsystems, divided by wall time).  The JSON line also carries p50/p99
+of the per-step safe-set latency, the HBM roofline of the dominant kernel
+(RK stage 2) from HIP-event timings of its launches, and the oracle's rate
+on the host CPU.
+
+Other modes (not the headline line): --mode batch (256 seeded subsystem
+solves, plain one-solve-per-call vs batched), --mode serve (Poisson request
+stream through the continuous-batching server), --mode warm (warm start and
+coarse-to-fine vs cold on the 4-D x-subsystem).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "warm"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--levels", type=int, default=2, help="1 = cold fine grid only")
+    ap.add_argument("--count", type=int, default=256, help="batch mode: problems")
+    ap.add_argument("--requests", type=int, default=3000, help="serve mode: requests")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve mode: req/s")
+    return ap.parse_args()
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+# ---------------------------------------------------------------------------
+# headline step
+# ---------------------------------------------------------------------------
+
+def build_step(torch, hjr, W, levels):
+    """Device inputs of the decomposed quadcopter: per subsystem a list of
+    (n, l, V) levels, coarse to fine."""
+    subs = [("x", W.quad_x4d, [21, 41]), ("y", W.quad_x4d, [21, 41]), ("z", W.quad_z2d, [51, 101])]
+    jobs = []
+    for name, mk, ns in subs:
+        ns = ns[-levels:]
+        lv = []
+        for n in ns:
+            P = mk(n, 0.5, name)
+            l = torch.tensor(P.l, dtype=torch.float32, device="cuda")
+            V = torch.empty_like(l)
+            lv.append((P.n, l, V))
+        spec = hjr.Spec.of(mk(ns[-1], 0.5, name))
+        jobs.append((name, spec, lv))
+    return jobs
+
+
+def run_step(hjr, torch, jobs, flags, chunk):
+    probs = [hjr.make_problem(spec, None, None, levels=lv) for _, spec, lv in jobs]
+    r, stats = hjr.solve_batch(probs, dtype=torch.float32, flags=flags, chunk=chunk)
+    return r, stats
+
+
+def cpu_baseline(seconds, W):
+    """The oracle as it stands, on a bounded sample of the workload: RK2
+    steps of the 41^4 x-subsystem from its cold start, single thread."""
+    from oracle import oracle as O
+    P = W.quad_x4d(41, 0.5)
+    g = O.make_grid(P.n, P.lo, P.hi)
+    d = O.make_dyn(P.kind, P.params)
+    alpha = O.lf_alpha(d, g, P.dlo, P.dhi)
+    dt = O.dt(g, alpha)
+    V = P.l.copy()
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        V, _ = O.iterate(d, g, P.dlo, P.dhi, alpha, dt, P.l, V)
+        steps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    return dict(value=P.size * steps / el, unit="cell-updates/s", cores=1, kind="oracle",
+                sample=f"{steps} RK2 steps of the 41^4 x-subsystem (FP64 oracle, 1 thread, "
+                       f"{el:.1f} s)")
+
+
+def mode_step(args, torch, hjr, W):
+    jobs = build_step(torch, hjr, W, args.levels)
+    for _ in range(args.warmup):
+        run_step(hjr, torch, jobs, 0, args.chunk)
+    torch.cuda.synchronize()
+    lat = []
+    cu = 0
+    kms = np.zeros(2)
+    kn = np.zeros(2)
+    it_levels = None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        r, stats = run_step(hjr, torch, jobs, hjr.FLAG_PROFILE, args.chunk)
+        lat.append((time.perf_counter() - s0) * 1e3)
+        if r != hjr.OK:
+            raise RuntimeError(f"solve did not converge: {stats}")
+        cu += sum(s["cell_updates"] for s in stats)
+        kms += np.asarray(stats[0]["kernel_ms"])  # batch-wide, same in every entry
+        kn += np.asarray(stats[0]["kernel_launches"])
+        it_levels = {name: s["level_iterations"][: len(lv)] for (name, _, lv), s in zip(jobs, stats)}
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    value = cu / el
+    cu_step = cu / args.steps
+    # dominant kernel: RK stage 2 reads Vhat, V, l and writes V (4 x 4 B per
+    # cell-update); stage 1 reads V and writes Vhat (8 B)
+    st2_bytes = cu * 16.0
+    achieved = st2_bytes / (kms[1] * 1e-3) / 1e9
+    st12 = cu * 24.0 / ((kms[0] + kms[1]) * 1e-3) / 1e9
+    out = {
+        "metric": "grid cell-updates/s",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "decomposed 10-D near-hover quadcopter, initial safe set: x,y 4-D 41^4 "
+                        "+ z 2-D 101^2, FP32 values / FP64 residual, dbar=0.5, ENO2+LF+TVD-RK2, "
+                        "CFL 0.8, tol 1e-4, " +
+                        ("coarse-to-fine from 21^4 / 51^2, " if args.levels == 2 else "cold fine grid, ") +
+                        "3 subsystems in one batched solve",
+            "cell_updates_per_step": cu_step,
+            "iterations_per_level": it_levels,
+        },
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_stage<float,2> (RK stage 2 + projection + residual)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_cell_update": 16,
+            "avg_launch_us": kms[1] / max(kn[1], 1) * 1e3,
+            "launches": int(kn[1]),
+            "stage1_plus_stage2_GBs": st12,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, W)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# batch mode: 256 seeded subsystem solves, plain vs batched
+# ---------------------------------------------------------------------------
+
+def mode_batch(args, torch, hjr, W):
+    man = W.batch_manifest(args.count, seed=0)
+    probs, keep = [], []
+    for e in man:
+        P = W.problem_from_manifest(e)
+        l = torch.tensor(P.l, dtype=torch.float32, device="cuda")
+        V = torch.empty_like(l)
+        keep.append((P, l, V))
+    # plain: one solve per call, per-iteration launches, host convergence read
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cu_plain = 0
+    for P, l, V in keep:
+        _, st = hjr.solve(hjr.Spec.of(P), l, V_out=V, flags=hjr.FLAG_NO_GRAPH | hjr.FLAG_NO_PIPELINE,
+                          chunk=1)
+        cu_plain += st["cell_updates"]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    V_plain = [V.clone() for _, _, V in keep]
+    # batched: one engine pass over all problems
+    probs = [hjr.make_problem(hjr.Spec.of(P), l, V) for P, l, V in keep]
+    t0 = time.perf_counter()
+    r, stats = hjr.solve_batch(probs, dtype=torch.float32, chunk=args.chunk)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    cu = sum(s["cell_updates"] for s in stats)
+    same = all(torch.equal(a, V) for a, (_, _, V) in zip(V_plain, keep))
+    return {
+        "metric": "safe-set updates/s (batched vs plain)", "mode": "batch",
+        "problems": len(keep), "dtype": "f32", "data": "synthetic",
+        "plain": {"seconds": t_plain, "updates_per_s": len(keep) / t_plain,
+                  "cell_updates_per_s": cu_plain / t_plain},
+        "batched": {"seconds": t_batch, "updates_per_s": len(keep) / t_batch,
+                    "cell_updates_per_s": cu / t_batch},
+        "bit_identical": bool(same),
+        "speedup": t_plain / t_batch,
+    }
+
+
+# ---------------------------------------------------------------------------
+# serve mode: Poisson request stream
+# ---------------------------------------------------------------------------
+
+def mode_serve(args, torch, hjr, W):
+    insts, reqs = W.serve_stream(args.requests, args.rate, seed=1)
+    specs = {}
+    ls = {}
+    for I in insts:
+        P = W.quad_x4d(I["n"]) if I["kind"] == W.QUAD_X4D else W.quad_z2d(I["n"])
+        specs[I["instance"]] = P
+        ls[I["instance"]] = P.l.astype(np.float32)
+    srv = hjr.Server(hbm_budget_bytes=8 << 30, max_active=64, chunk=args.chunk or 16)
+    seen = set()
+    tickets = []
+    t0 = time.perf_counter()
+    for r in reqs:
+        now = time.perf_counter() - t0
+        if r["t"] > now:
+            time.sleep(r["t"] - now)
+        P = specs[r["instance"]]
+        spec = hjr.Spec.of(P)
+        spec.dlo, spec.dhi = (-r["dbar"],), (r["dbar"],)
+        first = r["instance"] not in seen
+        seen.add(r["instance"])
+        tickets.append((r, srv.submit(r["instance"], spec, ls[r["instance"]] if first else None)))
+    replies = [(r, srv.wait(t)) for r, t in tickets]
+    wall = time.perf_counter() - t0
+    used, budget = srv.memory()
+    srv.close()
+    warm = [rep for r, rep in replies[200:]]
+    lat = [rep["latency_ms"] for rep in warm]
+    ok = sum(1 for _, rep in replies if rep["status"] == 0)
+    cu = sum(rep["iterations"] * specs[r["instance"]].size for r, rep in replies)
+    return {
+        "metric": "safe-set updates/s and p50/p99 latency (served)", "mode": "serve",
+        "requests": len(replies), "converged": ok, "rate_offered": args.rate,
+        "updates_per_s": len(replies) / wall, "cell_updates_per_s": cu / wall,
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": float(np.mean(lat))},
+        "warm_fraction": float(np.mean([rep["warm"] for rep in warm])),
+        "hbm_used_bytes": used, "hbm_budget_bytes": budget, "dtype": "f32", "data": "synthetic",
+    }
+
+
+# ---------------------------------------------------------------------------
+# warm-start / coarse-to-fine comparison on the 4-D x-subsystem
+# ---------------------------------------------------------------------------
+
+def mode_warm(args, torch, hjr, W):
+    def dev(P):
+        return torch.tensor(P.l, dtype=torch.float32, device="cuda")
+
+    P21, P41, P61 = W.quad_x4d(21, 0.5), W.quad_x4d(41, 0.5), W.quad_x4d(61, 0.5)
+    spec5 = hjr.Spec.of(P61)
+    ls = [dev(P21), dev(P41), dev(P61)]
+    out = {"metric": "iterations and time: warm / coarse-to-fine vs cold", "mode": "warm"}
+    t0 = time.perf_counter()
+    Vs, _, _, st = hjr.solve_levels(spec5, [P21.n, P41.n, P61.n], ls)
+    out["initial_coarse_to_fine"] = {"levels": st["level_iterations"][:3],
+                                     "seconds": time.perf_counter() - t0}
+    V61 = Vs[-1]
+    spec8 = hjr.Spec.of(W.quad_x4d(61, 0.8))
+    t0 = time.perf_counter()
+    Vc, stc = hjr.solve(spec8, ls[2])
+    out["update_cold_61"] = {"iterations": stc["iterations"], "seconds": time.perf_counter() - t0}
+    t0 = time.perf_counter()
+    Vw, stw = hjr.solve(spec8, ls[2], V0=V61)
+    out["update_warm_61"] = {"iterations": stw["iterations"], "seconds": time.perf_counter() - t0}
+    t0 = time.perf_counter()
+    V21 = hjr.interp(P61.n, V61, P21.n, P61.lo, P61.hi)
+    Vs2, _, _, st2 = hjr.solve_levels(spec8, [P21.n, P41.n, P61.n], ls, V0=V21)
+    out["update_restrict_warm_coarse_to_fine"] = {"levels": st2["level_iterations"][:3],
+                                                  "seconds": time.perf_counter() - t0}
+    a, b = Vc.cpu().numpy(), Vw.cpu().numpy()
+    out["warm_vs_cold_zero_level_disagreement"] = float(np.mean((a >= 0) != (b >= 0)))
+    out["c2f_vs_cold_zero_level_disagreement"] = float(np.mean((a >= 0) != (Vs2[-1].cpu().numpy() >= 0)))
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: each subsystem solve lives on one device "
+              "(multi-GPU sharding is not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2101_05916_amd import hjr
+    from paper_2101_05916_amd import workloads as W
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    hjr.lib()
+    fn = {"step": mode_step, "batch": mode_batch, "serve": mode_serve, "warm": mode_warm}[args.mode]
+    out = fn(args, torch, hjr, W)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

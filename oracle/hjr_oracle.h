@@ -1,0 +1,143 @@
+/*
+ * hjr_oracle.h -- plain, single-threaded FP64 reference for the grid-based
+ * Hamilton-Jacobi reachability safe-set solve.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this code; only the test-suite, the smoke check and the CPU
+ * baseline of the benchmark load it.  It shares no header, helper, table or
+ * constant with the HIP path.
+ *
+ * Sign convention.  The paper (Sec. II-A, eq. (1)-(2)) uses a cost c <= 0
+ * inside the constraint set, V = sup_d inf_u max_tau c(xi(tau)), projection
+ * max{c - V, .} and Hamiltonian min_u max_d <grad V, f>.  This code uses the
+ * negated quantities l = -c, V = -V_paper, so
+ *     0 = min{ l - V , D_tau V + max_u min_d <grad V, f> },
+ * the projection is V <- min(l, V), and the safe set is { V* >= 0 }.
+ *
+ * Discretisation (the paper does not name one): second-order ENO upwind
+ * derivatives (Osher & Shu 1991; Osher & Fedkiw, "Level Set Methods", ch. 3),
+ * global Lax-Friedrichs dissipation (Crandall-Lions / Osher-Shu), and the
+ * two-stage TVD Runge-Kutta step of Shu & Osher (1988), CFL number 0.8.
+ *
+ * All arrays are dense, row-major, last dimension fastest.
+ */
+#ifndef HJR_ORACLE_H
+#define HJR_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_QUAD_Z2D = 0, ORC_QUAD_X4D = 1, ORC_DI2X2 = 2 };
+
+enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_NOT_CONVERGED = 3 };
+
+typedef struct orc_grid {
+    int32_t ndim;
+    int32_t n[4];
+    double lo[4];
+    double hi[4];
+} orc_grid;
+
+/* Dynamics.  Parameters per kind:
+ *   ORC_QUAD_Z2D  state (z, vz):  p = {k, g, u_lo, u_hi}
+ *                 f = (vz, k*u - g + d),  u in [u_lo, u_hi], d channel 0.
+ *   ORC_QUAD_X4D  state (x, vx, theta, omega):  p = {g, d1, d0, n0, s_max}
+ *                 f = (vx + d, g*tan(theta), -d1*theta + omega, -d0*theta + n0*S)
+ *                 S in [-s_max, s_max], d channel 0.
+ *   ORC_DI2X2     two QUAD_Z2D copies "a" and "b" on a 4-D grid:
+ *                 p = {k_a, g_a, ulo_a, uhi_a, k_b, g_b, ulo_b, uhi_b,
+ *                      axis(z_a), axis(v_a), axis(z_b), axis(v_b)}
+ *                 (axes stored as doubles), d channel 0 acts on a, 1 on b.
+ */
+typedef struct orc_dyn {
+    int32_t kind;
+    int32_t pad_;
+    double p[16];
+} orc_dyn;
+
+/* Number of state dimensions / control inputs / disturbance channels. */
+int orc_state_dim(int kind);
+int orc_num_ctrl(int kind);
+int orc_num_dstb(int kind);
+
+/* f(x, u, d) written out component by component. */
+void orc_dynamics(const orc_dyn* dyn, const double* x, const double* u,
+                  const double* d, double* f);
+
+/* Control / disturbance box vertices: ctrl_lo/ctrl_hi per input. */
+void orc_ctrl_box(const orc_dyn* dyn, double* lo, double* hi);
+
+/* H(x, p) = max over u in U of min over d in D of p . f(x, u, d), by
+ * enumerating the vertices of the control and disturbance boxes (f is
+ * affine in u and in d, so the extrema sit on vertices). */
+double orc_hamiltonian(const orc_dyn* dyn, const double* x, const double* p,
+                       const double* dlo, const double* dhi);
+
+/* Node coordinate x_i[j] = lo_i + j * (hi_i - lo_i) / (n_i - 1). */
+double orc_coord(const orc_grid* g, int axis, int j);
+
+/* Global Lax-Friedrichs bounds: alpha_i = max over nodes and over the
+ * vertices of the control and disturbance boxes of |f_i|. */
+void orc_lf_alpha(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
+                  const double* dhi, double* alpha);
+
+/* dt = cfl / sum_i alpha_i / dx_i. */
+double orc_dt(const orc_grid* g, const double* alpha, double cfl);
+
+/* One-sided derivatives along a single line of n samples (n >= 3), with two
+ * linear-extrapolation ghost nodes on each side.  order 2 = ENO2, 1 = first
+ * order.  pm[j] = D^- at j, pp[j] = D^+ at j. */
+void orc_line_derivs(const double* v, int n, double h, int order, double* pm,
+                     double* pp);
+
+/* Spatial operator L(V) = H(x, (p+ + p-)/2) + sum_i alpha_i (p+_i - p-_i)/2
+ * at every node. */
+void orc_spatial_op(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
+                    const double* dhi, const double* alpha, int order,
+                    const double* V, double* L);
+
+/* One full iteration: Vhat = V + dt L(V); Vtil = Vhat + dt L(Vhat);
+ * Vnew = min(l, (V + Vtil)/2).  Returns max |Vnew - V|.  Vnew may not alias V. */
+double orc_iterate(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
+                   const double* dhi, const double* alpha, double dt,
+                   int order, const double* l, const double* V, double* Vnew);
+
+/* The same iteration evaluated at one node only (flat index idx), from the
+ * full array V.  Used to check a device result at sampled nodes of a grid too
+ * large to iterate here. */
+double orc_iterate_at(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
+                      const double* dhi, const double* alpha, double dt,
+                      int order, const double* l, const double* V,
+                      int64_t idx);
+
+/* Time-marched solve of the variational inequality until max|dV| < tol.
+ *   V0 == NULL: cold start V0 = l.  Otherwise V <- min(l, V0) (warm start).
+ *   res_hist (nullable, length max_iter): residual of every iteration.
+ *   max_rise (nullable): max over iterations and nodes of V_{k+1} - V_k.
+ * Returns ORC_OK, ORC_NOT_CONVERGED (outputs hold the last iterate) or
+ * ORC_EINVAL. */
+int orc_solve(const orc_dyn* dyn, const orc_grid* g, const double* l,
+              const double* V0, const double* dlo, const double* dhi,
+              double tol, double cfl, int order, int64_t max_iter,
+              double* V_out, int64_t* iterations, double* residual,
+              double* dt_out, double* alpha_out, double* res_hist,
+              double* max_rise);
+
+/* Multilinear interpolation between two grids over the same box, with
+ * integer index arithmetic and FP64 weights; corners summed in row-major
+ * order of their offsets.  Returns ORC_EINVAL if the boxes differ. */
+int orc_interp(const orc_grid* src, const double* Vs, const orc_grid* dst,
+               double* Vd);
+
+/* Refinement mask: cell c in [0, n-2]^D is 1 iff one of its 2^D corner nodes
+ * has V >= 0 and another has V < 0.  Returns the number of marked cells. */
+int64_t orc_refine_mask(const orc_grid* g, const double* V, uint8_t* mask);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

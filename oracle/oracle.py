@@ -1,0 +1,237 @@
+"""ctypes wrapper of the FP64 CPU oracle (``hjr_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+baseline leg of the benchmark may import this module.  The product package
+never imports it, and it imports nothing from the product package: the two
+sides meet only through the seeded input generators, which hold none of the
+method's arithmetic.
+
+Every function mirrors one entry of ``hjr_oracle.h``; inputs are numpy
+arrays (converted to contiguous float64), outputs are numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+_SRC = os.path.join(_HERE, "hjr_oracle.c")
+
+QUAD_Z2D, QUAD_X4D, DI2X2 = 0, 1, 2
+OK, EINVAL, NOT_CONVERGED = 0, 1, 3
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C11, FP64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off",
+            "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm",
+        ])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Grid(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 4),
+                ("lo", C.c_double * 4), ("hi", C.c_double * 4)]
+
+
+class Dyn(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad_", C.c_int32), ("p", C.c_double * 16)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        L = C.CDLL(_LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        gp, yp = C.POINTER(Grid), C.POINTER(Dyn)
+        L.orc_hamiltonian.restype = C.c_double
+        L.orc_hamiltonian.argtypes = [yp, dp, dp, dp, dp]
+        L.orc_dynamics.restype = None
+        L.orc_dynamics.argtypes = [yp, dp, dp, dp, dp]
+        L.orc_lf_alpha.restype = None
+        L.orc_lf_alpha.argtypes = [yp, gp, dp, dp, dp]
+        L.orc_dt.restype = C.c_double
+        L.orc_dt.argtypes = [gp, dp, C.c_double]
+        L.orc_line_derivs.restype = None
+        L.orc_line_derivs.argtypes = [dp, C.c_int, C.c_double, C.c_int, dp, dp]
+        L.orc_spatial_op.restype = None
+        L.orc_spatial_op.argtypes = [yp, gp, dp, dp, dp, C.c_int, dp, dp]
+        L.orc_iterate.restype = C.c_double
+        L.orc_iterate.argtypes = [yp, gp, dp, dp, dp, C.c_double, C.c_int, dp, dp, dp]
+        L.orc_iterate_at.restype = C.c_double
+        L.orc_iterate_at.argtypes = [yp, gp, dp, dp, dp, C.c_double, C.c_int, dp, dp,
+                                     C.c_int64]
+        L.orc_solve.restype = C.c_int
+        L.orc_solve.argtypes = [yp, gp, dp, dp, dp, dp, C.c_double, C.c_double, C.c_int,
+                                C.c_int64, dp, C.POINTER(C.c_int64), dp, dp, dp, dp, dp]
+        L.orc_interp.restype = C.c_int
+        L.orc_interp.argtypes = [gp, dp, gp, dp]
+        L.orc_refine_mask.restype = C.c_int64
+        L.orc_refine_mask.argtypes = [gp, dp, C.POINTER(C.c_uint8)]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_grid(n, lo, hi) -> Grid:
+    g = Grid()
+    g.ndim = len(n)
+    for i in range(len(n)):
+        g.n[i] = int(n[i])
+        g.lo[i] = float(lo[i])
+        g.hi[i] = float(hi[i])
+    return g
+
+
+def make_dyn(kind: int, params) -> Dyn:
+    d = Dyn()
+    d.kind = kind
+    for i, v in enumerate(params):
+        d.p[i] = float(v)
+    return d
+
+
+def _dbounds(dlo, dhi):
+    lo = np.zeros(4)
+    hi = np.zeros(4)
+    dlo = np.atleast_1d(np.asarray(dlo, dtype=np.float64))
+    dhi = np.atleast_1d(np.asarray(dhi, dtype=np.float64))
+    lo[: len(dlo)] = dlo
+    hi[: len(dhi)] = dhi
+    return lo, hi
+
+
+def hamiltonian(dyn: Dyn, x, p, dlo, dhi) -> float:
+    x = _f64(np.resize(np.asarray(x, dtype=np.float64), 4))
+    p = _f64(np.resize(np.asarray(p, dtype=np.float64), 4))
+    lo, hi = _dbounds(dlo, dhi)
+    return lib().orc_hamiltonian(C.byref(dyn), _dp(x), _dp(p), _dp(lo), _dp(hi))
+
+
+def dynamics(dyn: Dyn, x, u, d):
+    x = _f64(np.resize(np.asarray(x, dtype=np.float64), 4))
+    u = _f64(np.resize(np.asarray(u, dtype=np.float64), 4))
+    d = _f64(np.resize(np.asarray(d, dtype=np.float64), 4))
+    f = np.zeros(4)
+    lib().orc_dynamics(C.byref(dyn), _dp(x), _dp(u), _dp(d), _dp(f))
+    return f
+
+
+def lf_alpha(dyn: Dyn, grid: Grid, dlo, dhi):
+    lo, hi = _dbounds(dlo, dhi)
+    a = np.zeros(4)
+    lib().orc_lf_alpha(C.byref(dyn), C.byref(grid), _dp(lo), _dp(hi), _dp(a))
+    return a[: grid.ndim]
+
+
+def dt(grid: Grid, alpha, cfl: float = 0.8) -> float:
+    a = np.zeros(4)
+    a[: len(alpha)] = alpha
+    return lib().orc_dt(C.byref(grid), _dp(a), cfl)
+
+
+def line_derivs(v, h: float, order: int = 2):
+    v = _f64(v)
+    pm = np.zeros_like(v)
+    pp = np.zeros_like(v)
+    lib().orc_line_derivs(_dp(v), len(v), h, order, _dp(pm), _dp(pp))
+    return pm, pp
+
+
+def spatial_op(dyn, grid, dlo, dhi, alpha, V, order=2):
+    V = _f64(V)
+    lo, hi = _dbounds(dlo, dhi)
+    a = np.zeros(4)
+    a[: len(alpha)] = alpha
+    L = np.zeros_like(V)
+    lib().orc_spatial_op(C.byref(dyn), C.byref(grid), _dp(lo), _dp(hi), _dp(a), order,
+                         _dp(V), _dp(L))
+    return L
+
+
+def iterate(dyn, grid, dlo, dhi, alpha, dt_, l, V, order=2):
+    V = _f64(V)
+    l = _f64(l)
+    lo, hi = _dbounds(dlo, dhi)
+    a = np.zeros(4)
+    a[: len(alpha)] = alpha
+    Vn = np.zeros_like(V)
+    r = lib().orc_iterate(C.byref(dyn), C.byref(grid), _dp(lo), _dp(hi), _dp(a), dt_,
+                          order, _dp(l), _dp(V), _dp(Vn))
+    return Vn, r
+
+
+def iterate_at(dyn, grid, dlo, dhi, alpha, dt_, l, V, idx, order=2) -> float:
+    V = _f64(V)
+    l = _f64(l)
+    lo, hi = _dbounds(dlo, dhi)
+    a = np.zeros(4)
+    a[: len(alpha)] = alpha
+    return lib().orc_iterate_at(C.byref(dyn), C.byref(grid), _dp(lo), _dp(hi), _dp(a),
+                                dt_, order, _dp(l), _dp(V), int(idx))
+
+
+def solve(dyn, grid, l, dlo, dhi, tol=1e-4, V0=None, cfl=0.8, order=2,
+          max_iter=100000, history=False):
+    """Returns dict(V, status, iterations, residual, dt, alpha, res_hist, max_rise)."""
+    l = _f64(l)
+    lo, hi = _dbounds(dlo, dhi)
+    V = np.zeros_like(l)
+    it = C.c_int64(0)
+    res = C.c_double(0)
+    dt_ = C.c_double(0)
+    a = np.zeros(4)
+    hist = np.zeros(max(int(max_iter), 1)) if history else None
+    rise = C.c_double(0)
+    v0p = None
+    if V0 is not None:
+        V0 = _f64(V0)
+        v0p = _dp(V0)
+    st = lib().orc_solve(C.byref(dyn), C.byref(grid), _dp(l), v0p, _dp(lo), _dp(hi),
+                         float(tol), float(cfl), int(order), int(max_iter), _dp(V),
+                         C.byref(it), C.byref(res), C.byref(dt_), _dp(a),
+                         _dp(hist) if history else None, C.byref(rise))
+    out = dict(V=V, status=st, iterations=it.value, residual=res.value, dt=dt_.value,
+               alpha=a[: grid.ndim].copy(), max_rise=rise.value)
+    if history:
+        out["res_hist"] = hist[: it.value].copy()
+    return out
+
+
+def interp(src: Grid, Vs, dst: Grid):
+    Vs = _f64(Vs)
+    n = [dst.n[i] for i in range(dst.ndim)]
+    Vd = np.zeros(int(np.prod(n)))
+    st = lib().orc_interp(C.byref(src), _dp(Vs), C.byref(dst), _dp(Vd))
+    if st != OK:
+        raise ValueError("orc_interp: grids do not share a box")
+    return Vd
+
+
+def refine_mask(grid: Grid, V):
+    V = _f64(V)
+    nc = [grid.n[i] - 1 for i in range(grid.ndim)]
+    m = np.zeros(int(np.prod(nc)), dtype=np.uint8)
+    cnt = lib().orc_refine_mask(C.byref(grid), _dp(V),
+                                m.ctypes.data_as(C.POINTER(C.c_uint8)))
+    return m, int(cnt)

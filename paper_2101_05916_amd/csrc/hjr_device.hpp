@@ -1,0 +1,131 @@
+// hjr_device.hpp -- data shared between the host engine and the HIP kernels
+// of libhjr (layouts of the device-resident problem table, per-problem
+// state, chunk control and residual buffers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hjr {
+
+constexpr int kBlock = 256;          // threads per workgroup of the utility kernels
+// The RK-stage kernels run one wavefront per workgroup: a tile's LDS
+// barriers then synchronise a single wave, and each CU interleaves ~20
+// independent waves to hide memory latency.
+#ifndef HJR_STAGE_BLOCK
+#define HJR_STAGE_BLOCK 64
+#endif
+#ifndef HJR_PLANE_NODES_PT
+#define HJR_PLANE_NODES_PT 8
+#endif
+constexpr int kStageBlock = HJR_STAGE_BLOCK;
+constexpr int kNodesPerThread = 512 / HJR_STAGE_BLOCK > 1 ? 512 / HJR_STAGE_BLOCK : 2;  // nodes per thread of a flat tile
+constexpr int kTile = kStageBlock * kNodesPerThread;  // nodes per flat tile
+constexpr int kResSubs = 64;         // residual atomics spread over 64 words
+constexpr int kMaxChunk = 256;       // iterations per chunk, upper bound
+
+// Plane tiles: one workgroup stages the two fastest axes of a tile in LDS
+// with a row stride fixed at compile time, so every in-plane neighbour is a
+// constant LDS offset.  kPlaneElems bounds (rows + 4) * stride.
+constexpr int kRowStrideS = 72;      // planes whose last axis has <= 68 nodes
+constexpr int kRowStrideL = 208;     // planes whose last axis has <= 204 nodes
+constexpr int kPlaneNodesPT = HJR_PLANE_NODES_PT;   // nodes per thread of a plane tile
+constexpr int kPlaneStagePT = 2 * kPlaneNodesPT;    // staged elements per thread of a plane tile
+constexpr int kPlaneElems = kPlaneStagePT * kStageBlock + 4 * kRowStrideL;  // LDS elements of one block
+
+enum TilePath : int32_t { kPathFlat = 0, kPathPlaneS = 1, kPathPlaneL = 2 };
+
+// Division of a 31-bit unsigned index by a runtime divisor d >= 2 with one
+// 32x32->hi multiply: q = mulhi(x, m) >> s, with s = ceil(log2 d) - 1 and
+// m = ceil(2^(32+s) / d).  Exact for x < 2^31 (Granlund & Montgomery 1994,
+// "Division by invariant integers using multiplication", with the shift
+// reduced by one so that m fits 32 bits).
+struct FastDiv {
+    uint32_t d;
+    uint32_t m;
+    uint32_t s;
+    uint32_t pad;
+};
+
+// Static description of one problem in the batch (written by the host).
+struct ProbDesc {
+    int32_t kind;
+    int32_t ndim;
+    int32_t order;
+    int32_t path;            // TilePath
+    int32_t n[4];
+    int64_t N;
+    int64_t stride[4];
+    FastDiv div[4];          // divisors n[1..ndim-1] used to split a flat index
+    // plane tiles: rows per tile along axis ndim-2, and chunks per plane
+    int32_t rows;
+    int32_t chunks;
+    FastDiv div_chunks;      // divisor `chunks`
+    FastDiv div_last;        // divisor n[ndim-1]
+    double lo[4];
+    double h[4];
+    double hih[4];           // 0.5 / h
+    float lo_f[4];
+    float h_f[4];
+    float hih_f[4];
+    double hc_d[16];         // Hamiltonian constants with 0.5/h folded in (see hjr_stencil.hpp)
+    float hc_f[16];
+    double par[16];
+    double dlo[2];
+    double dhi[2];
+    double tol;
+    double cfl;
+    void* V;                 // value, updated in place
+    const void* l;           // constraint
+    void* Vhat;              // stage-1 scratch
+    void* table;             // per-axis lookup table (g tan(theta) for QUAD_X4D)
+    int64_t tile_begin;      // first global tile of this problem
+    int64_t ntiles;
+};
+
+// Device-written per-problem quantities (once per level).
+struct ProbState {
+    uint64_t alpha_bits[4];  // max-reduction of |f_i| as IEEE bit patterns
+    double alpha[4];
+    double dt;
+    double ah[4];            // alpha * 0.5 / h
+    float ah_f[4];
+    float dt_f;
+    float pad_f[3];
+    uint64_t mask_count;
+    double pad[1];
+};
+
+// Per-chunk header and per-problem control (written by the host each chunk).
+struct ChunkHdr {
+    int64_t total_tiles;
+    int32_t nprob;
+    int32_t pad;
+};
+
+struct ProbCtl {
+    int32_t limit;   // iterations this problem may take in this chunk (0..K)
+    int32_t fresh;   // 1 = first chunk of a level: no carried residual
+};
+
+// Kernel argument block for the iteration kernels.
+struct ChunkArgs {
+    const ProbDesc* probs;
+    ProbState* states;
+    const ChunkHdr* hdr;
+    const ProbCtl* ctl;
+    uint64_t* res;       // [cap][K+1][kResSubs] residual bit patterns, this parity
+    const double* prev;  // [cap][K] reduced residuals of the previous chunk
+    double* compact;     // [cap][K] reduced residuals of this chunk (output)
+    int32_t K;
+    int32_t cap;
+    int32_t slot;        // iteration index within the chunk
+    int32_t pad;
+};
+
+__host__ __device__ inline int64_t res_index(int p, int s, int sub, int K)
+{
+    return ((int64_t)p * (K + 1) + s) * kResSubs + sub;
+}
+
+}  // namespace hjr

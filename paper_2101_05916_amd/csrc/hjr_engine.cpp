@@ -1,0 +1,621 @@
+// hjr_engine.cpp -- chunked, pipelined driver of the iteration kernels.
+#include "hjr_engine.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "hjr_launch.hpp"
+
+namespace hjr {
+
+#define HJR_TRY(expr)                               \
+    do {                                            \
+        hipError_t e_ = (expr);                     \
+        if (e_ != hipSuccess) {                     \
+            last_err_ = e_;                         \
+            return HJR_EDEVICE;                     \
+        }                                           \
+    } while (0)
+
+// ------------------------------------------------------------------------
+// helpers
+// ------------------------------------------------------------------------
+
+bool grid_valid(const hjr_grid& g)
+{
+    if (g.ndim < 1 || g.ndim > 4) return false;
+    int64_t N = 1;
+    for (int i = 0; i < g.ndim; i++) {
+        if (g.n[i] < 3) return false;
+        if (!(g.lo[i] < g.hi[i])) return false;
+        if (!std::isfinite(g.lo[i]) || !std::isfinite(g.hi[i])) return false;
+        N *= g.n[i];
+        if (N > (int64_t(1) << 31) - 1) return false;  // flat indices are 31-bit
+    }
+    return true;
+}
+
+int64_t grid_size(const hjr_grid& g)
+{
+    int64_t N = 1;
+    for (int i = 0; i < g.ndim; i++) N *= g.n[i];
+    return N;
+}
+
+int dyn_dim(int kind)
+{
+    switch (kind) {
+    case HJR_QUAD_Z2D: return 2;
+    case HJR_QUAD_X4D: return 4;
+    case HJR_DI2X2: return 4;
+    default: return 0;
+    }
+}
+
+int dyn_channels(int kind)
+{
+    switch (kind) {
+    case HJR_QUAD_Z2D: return 1;
+    case HJR_QUAD_X4D: return 1;
+    case HJR_DI2X2: return 2;
+    default: return 0;
+    }
+}
+
+bool dyn_valid(const hjr_dyn& d, const hjr_grid& g)
+{
+    const int D = dyn_dim(d.kind);
+    if (D == 0 || D != g.ndim) return false;
+    for (int i = 0; i < 16; i++)
+        if (!std::isfinite(d.p[i])) return false;
+    if (d.kind == HJR_QUAD_Z2D && !(d.p[2] <= d.p[3])) return false;
+    if (d.kind == HJR_QUAD_X4D && !(d.p[4] >= 0.0)) return false;
+    if (d.kind == HJR_QUAD_X4D) {
+        // tan(theta) must stay finite on the grid
+        const double half_pi = 1.5707963267948966;
+        if (!(g.lo[2] > -half_pi && g.hi[2] < half_pi)) return false;
+    }
+    if (d.kind == HJR_DI2X2) {
+        if (!(d.p[2] <= d.p[3]) || !(d.p[6] <= d.p[7])) return false;
+        int seen = 0;
+        for (int i = 8; i < 12; i++) {
+            const double a = d.p[i];
+            if (a != std::floor(a) || a < 0 || a > 3) return false;
+            seen |= 1 << (int)a;
+        }
+        if (seen != 15) return false;
+    }
+    return true;
+}
+
+size_t elem_size(int dtype)
+{
+    return dtype == HJR_F64 ? sizeof(double) : sizeof(float);
+}
+
+FastDiv make_fastdiv(uint32_t d)
+{
+    FastDiv f{d, 0, 0, 0};
+    if (d < 2) return f;  // never used: every axis has >= 3 nodes
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < d) l++;  // l = ceil(log2 d)
+    const uint32_t s = l - 1;
+    const uint64_t num = uint64_t(1) << (32 + s);
+    f.m = (uint32_t)((num + d - 1) / d);
+    f.s = s;
+    return f;
+}
+
+static size_t align256(size_t x)
+{
+    return (x + 255) & ~size_t(255);
+}
+
+// ------------------------------------------------------------------------
+// Engine
+// ------------------------------------------------------------------------
+
+Engine::Engine(const EngineCfg& cfg) : cfg_(cfg)
+{
+    if (cfg_.K < 1) cfg_.K = 1;
+    if (cfg_.K > kMaxChunk) cfg_.K = kMaxChunk;
+    if (cfg_.cap < 1) cfg_.cap = 1;
+    depth_ = (cfg_.flags & HJR_FLAG_NO_PIPELINE) ? 0 : 1;
+    profile_ = (cfg_.flags & HJR_FLAG_PROFILE) != 0;
+    use_graph_ = !(cfg_.flags & HJR_FLAG_NO_GRAPH) && !profile_;
+}
+
+Engine::~Engine()
+{
+    if (stream_) (void)hipStreamSynchronize(stream_);
+    for (auto& f : flights_)
+        if (f.ev) (void)hipEventDestroy(f.ev);
+    for (int p = 0; p < 2; p++) {
+        for (auto& g : graphs_[p]) (void)hipGraphExecDestroy(g.second);
+        if (h_desc_[p]) (void)hipHostFree(h_desc_[p]);
+        if (h_ctl_[p]) (void)hipHostFree(h_ctl_[p]);
+        if (h_compact_[p]) (void)hipHostFree(h_compact_[p]);
+        if (desc_ev_[p]) (void)hipEventDestroy(desc_ev_[p]);
+        for (hipEvent_t e : prof_ev_[p]) (void)hipEventDestroy(e);
+    }
+    if (own_arena_ && arena_) (void)hipFree(arena_);
+}
+
+size_t Engine::table_bytes(int cap, int K)
+{
+    if (K > kMaxChunk) K = kMaxChunk;
+    size_t b = 0;
+    b += align256(sizeof(ProbDesc) * cap);
+    b += align256(sizeof(ProbState) * cap);
+    b += 2 * align256(256 + sizeof(ProbCtl) * cap);
+    b += 2 * align256(sizeof(uint64_t) * (size_t)cap * (K + 1) * kResSubs);
+    b += 2 * align256(sizeof(double) * (size_t)cap * K);
+    b += align256(sizeof(uint64_t) * 4 * cap);
+    return b;
+}
+
+hjr_status Engine::init(hipStream_t stream, void* arena)
+{
+    stream_ = stream;
+    const int cap = cfg_.cap, K = cfg_.K;
+    const size_t tb = table_bytes(cap, K);
+    if (!arena) {
+        HJR_TRY(hipMalloc(&arena_, tb));
+        own_arena_ = true;
+    } else {
+        arena_ = arena;
+    }
+    char* p = (char*)arena_;
+    auto take = [&](size_t bytes) {
+        char* r = p;
+        p += align256(bytes);
+        return (void*)r;
+    };
+    d_desc_ = (ProbDesc*)take(sizeof(ProbDesc) * cap);
+    d_state_ = (ProbState*)take(sizeof(ProbState) * cap);
+    ctl_bytes_ = 256 + sizeof(ProbCtl) * cap;
+    for (int q = 0; q < 2; q++) {
+        d_hdr_[q] = (ChunkHdr*)take(ctl_bytes_);
+        d_ctl_[q] = (ProbCtl*)((char*)d_hdr_[q] + 256);
+    }
+    for (int q = 0; q < 2; q++) d_res_[q] = (uint64_t*)take(sizeof(uint64_t) * (size_t)cap * (K + 1) * kResSubs);
+    for (int q = 0; q < 2; q++) d_compact_[q] = (double*)take(sizeof(double) * (size_t)cap * K);
+    d_mask_counts_ = (uint64_t*)take(sizeof(uint64_t) * 4 * cap);
+
+    for (int q = 0; q < 2; q++) {
+        HJR_TRY(hipHostMalloc((void**)&h_desc_[q], sizeof(ProbDesc) * cap, hipHostMallocDefault));
+        HJR_TRY(hipHostMalloc((void**)&h_ctl_[q], ctl_bytes_, hipHostMallocDefault));
+        HJR_TRY(hipHostMalloc((void**)&h_compact_[q], sizeof(double) * (size_t)cap * K,
+                              hipHostMallocDefault));
+        std::memset(h_desc_[q], 0, sizeof(ProbDesc) * cap);
+        std::memset(h_ctl_[q], 0, ctl_bytes_);
+        HJR_TRY(hipEventCreateWithFlags(&desc_ev_[q], hipEventDisableTiming));
+        HJR_TRY(hipEventRecord(desc_ev_[q], stream_));
+    }
+    // zero the residual histories and mask counters once
+    for (int q = 0; q < 2; q++)
+        HJR_TRY(launch_fill_u64(stream_, (uint64_t*)d_compact_[q], (int64_t)cap * K, 0));
+    HJR_TRY(launch_fill_u64(stream_, d_mask_counts_, 4 * (int64_t)cap, 0));
+
+    if (cfg_.grid > 0) {
+        grid_ = cfg_.grid;
+    } else {
+        int dev = 0, cus = 0;
+        HJR_TRY(hipGetDevice(&dev));
+        HJR_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        grid_ = cus * stage_blocks_per_cu(cfg_.dtype);
+    }
+    grid_ = std::max(8, (grid_ + 7) / 8 * 8);
+    if (profile_)
+        for (int q = 0; q < 2; q++) {
+            prof_ev_[q].resize(4 * (size_t)K);
+            for (auto& e : prof_ev_[q]) HJR_TRY(hipEventCreate(&e));
+        }
+    slots_.assign(cap, nullptr);
+    table_dirty_ = true;
+    return HJR_OK;
+}
+
+hjr_status Engine::reset(const EngineCfg& c)
+{
+    cfg_.order = c.order;
+    cfg_.cfl = c.cfl;
+    cfg_.max_iter = c.max_iter;
+    for (auto& f : flights_)
+        if (f.ev) (void)hipEventDestroy(f.ev);
+    flights_.clear();
+    slots_.assign(cfg_.cap, nullptr);
+    running_ = 0;
+    table_dirty_ = true;
+    prof_ms_[0] = prof_ms_[1] = 0.0;
+    prof_n_[0] = prof_n_[1] = 0;
+    HJR_TRY(launch_fill_u64(stream_, d_mask_counts_, 4 * (int64_t)cfg_.cap, 0));
+    return HJR_OK;
+}
+
+int Engine::free_slots() const
+{
+    int n = 0;
+    for (auto* j : slots_) n += (j == nullptr);
+    return n;
+}
+
+void Engine::fill_desc(const Job* j, ProbDesc& P) const
+{
+    std::memset(&P, 0, sizeof(P));
+    const Level& L = j->lev[j->cur];
+    const hjr_grid& g = L.grid;
+    P.kind = j->dyn.kind;
+    P.ndim = g.ndim;
+    P.order = cfg_.order;
+    int64_t st = 1;
+    for (int a = g.ndim - 1; a >= 0; a--) {
+        P.n[a] = g.n[a];
+        P.stride[a] = st;
+        st *= g.n[a];
+        P.div[a] = make_fastdiv((uint32_t)g.n[a]);
+        P.lo[a] = g.lo[a];
+        P.h[a] = (g.hi[a] - g.lo[a]) / (double)(g.n[a] - 1);
+    }
+    P.N = st;
+    for (int i = 0; i < 16; i++) P.par[i] = j->dyn.p[i];
+    for (int c = 0; c < 2; c++) {
+        P.dlo[c] = j->d[c].lo;
+        P.dhi[c] = j->d[c].hi;
+    }
+    P.tol = j->tol;
+    P.cfl = cfg_.cfl;
+    P.V = L.V;
+    P.l = L.l;
+    P.Vhat = j->Vhat;
+    P.table = j->table;
+    const int D = g.ndim;
+    for (int a = 0; a < D; a++) {
+        P.hih[a] = 0.5 / P.h[a];
+        P.lo_f[a] = (float)P.lo[a];
+        P.h_f[a] = (float)P.h[a];
+        P.hih_f[a] = (float)P.hih[a];
+    }
+    // Hamiltonian constants with the 0.5/h factors folded in
+    double* hc = P.hc_d;
+    const double* p = P.par;
+    if (P.kind == HJR_QUAD_Z2D) {
+        const double ku_lo = p[0] * p[2], ku_hi = p[0] * p[3];
+        const double dl = std::min(P.dlo[0], P.dhi[0]), dh = std::max(P.dlo[0], P.dhi[0]);
+        hc[0] = P.hih[0] * P.lo[1];
+        hc[1] = P.hih[0] * P.h[1];
+        hc[2] = (std::max(ku_lo, ku_hi) + dl - p[1]) * P.hih[1];
+        hc[3] = (std::min(ku_lo, ku_hi) + dh - p[1]) * P.hih[1];
+    } else if (P.kind == HJR_QUAD_X4D) {
+        const double g_ = p[0], d1 = p[1], d0 = p[2], n0 = p[3], sm = p[4];
+        hc[0] = P.hih[0] * P.lo[1];
+        hc[1] = P.hih[0] * P.h[1];
+        hc[2] = P.dlo[0] * P.hih[0];
+        hc[3] = P.dhi[0] * P.hih[0];
+        hc[4] = P.hih[2] * (P.lo[3] - d1 * P.lo[2]);
+        hc[5] = P.hih[2] * P.h[3];
+        hc[6] = P.hih[2] * d1 * P.h[2];
+        hc[7] = d0 * P.hih[3] * P.lo[2];
+        hc[8] = d0 * P.hih[3] * P.h[2];
+        hc[9] = n0 * sm * P.hih[3];
+        (void)g_;
+    }
+    for (int i = 0; i < 16; i++) P.hc_f[i] = (float)P.hc_d[i];
+    // tile shape: LDS plane tiles over the two fastest axes when they fit,
+    // else flat tiles of kTile consecutive nodes
+    P.path = kPathFlat;
+    P.ntiles = (P.N + kTile - 1) / kTile;
+    const bool plane_kind = (P.kind == HJR_QUAD_Z2D || P.kind == HJR_QUAD_X4D) &&
+                            !(cfg_.flags & HJR_FLAG_FLAT_TILES);
+    // plane tiles address with 32-bit byte offsets
+    const bool fits32 = (double)P.N * (double)elem_size(cfg_.dtype) < 4294967296.0;
+    if (plane_kind && fits32 && (D == 2 || D == 4)) {
+        const int nr = g.n[D - 2], nc = g.n[D - 1];
+        int rs = 0;
+        if (nc + 4 <= kRowStrideS) {
+            rs = kRowStrideS;
+            P.path = kPathPlaneS;
+        } else if (nc + 4 <= kRowStrideL) {
+            rs = kRowStrideL;
+            P.path = kPathPlaneL;
+        }
+        if (rs) {
+            // rows per tile: at most kPlaneNodesPT nodes and kPlaneStagePT
+            // staged elements per thread, and the LDS block within kPlaneElems
+            int want = std::min(kPlaneElems / rs - 4, kPlaneNodesPT * kStageBlock / nc);
+            want = std::min(want, kPlaneStagePT * kStageBlock / nc - 4);
+            want = std::max(want, 1);
+            const int chunks = (nr + want - 1) / want;
+            P.rows = (nr + chunks - 1) / chunks;
+            P.chunks = chunks;
+            P.div_chunks = make_fastdiv((uint32_t)std::max(chunks, 2));
+            P.div_last = make_fastdiv((uint32_t)nc);
+            int64_t outer = 1;
+            for (int a = 0; a < D - 2; a++) outer *= g.n[a];
+            P.ntiles = outer * chunks;
+        }
+    }
+}
+
+hjr_status Engine::setup_level(Job* j)
+{
+    const Level& L = j->lev[j->cur];
+    ProbDesc P;
+    fill_desc(j, P);
+    if (j->cur == 0) {
+        HJR_TRY(launch_init(stream_, cfg_.dtype, L.V, L.l, j->V0, P.N));
+    } else {
+        const Level& prev = j->lev[j->cur - 1];
+        HJR_TRY(launch_interp(stream_, cfg_.dtype, prev.grid, prev.V, L.grid, L.V, L.l));
+    }
+    HJR_TRY(launch_level_setup(stream_, cfg_.dtype, P, &d_state_[j->slot]));
+    j->sched = 0;
+    j->fresh = true;
+    j->level_start_chunk = chunk_;
+    table_dirty_ = true;
+    return HJR_OK;
+}
+
+hjr_status Engine::add(Job* j)
+{
+    int s = -1;
+    for (int i = 0; i < cfg_.cap; i++)
+        if (!slots_[i]) {
+            s = i;
+            break;
+        }
+    if (s < 0) return HJR_EBUSY;
+    slots_[s] = j;
+    j->slot = s;
+    j->cur = 0;
+    j->done = false;
+    j->status = HJR_OK;
+    for (int k = 0; k < 4; k++) j->level_iters[k] = 0;
+    running_++;
+    HJR_TRY(launch_fill_u64(stream_, d_mask_counts_ + 4 * (int64_t)s, 4, 0));
+    return setup_level(j);
+}
+
+hjr_status Engine::upload_table()
+{
+    const int q = desc_par_;
+    desc_par_ ^= 1;
+    HJR_TRY(hipEventSynchronize(desc_ev_[q]));  // staging q no longer being read
+    ProbDesc* h = h_desc_[q];
+    int64_t total = 0;
+    for (int s = 0; s < cfg_.cap; s++) {
+        Job* j = slots_[s];
+        if (j && !j->done) {
+            fill_desc(j, h[s]);
+        } else {
+            std::memset(&h[s], 0, sizeof(ProbDesc));
+            h[s].tol = 1.0;
+            h[s].ntiles = 0;
+        }
+        h[s].tile_begin = total;
+        total += h[s].ntiles;
+    }
+    total_tiles_ = total;
+    HJR_TRY(hipMemcpyAsync(d_desc_, h, sizeof(ProbDesc) * cfg_.cap, hipMemcpyHostToDevice, stream_));
+    HJR_TRY(hipEventRecord(desc_ev_[q], stream_));
+    table_dirty_ = false;
+    return HJR_OK;
+}
+
+ChunkArgs Engine::args(int par, int slot) const
+{
+    ChunkArgs a;
+    a.probs = d_desc_;
+    a.states = d_state_;
+    a.hdr = d_hdr_[par];
+    a.ctl = d_ctl_[par];
+    a.res = d_res_[par];
+    a.prev = d_compact_[par ^ 1];
+    a.compact = d_compact_[par];
+    a.K = cfg_.K;
+    a.cap = cfg_.cap;
+    a.slot = slot;
+    a.pad = 0;
+    return a;
+}
+
+hjr_status Engine::enqueue_chunk_body(int par)
+{
+    HJR_TRY(launch_prologue(stream_, args(par, 0)));
+    for (int s = 0; s < cfg_.K; s++) {
+        const ChunkArgs a = args(par, s);
+        for (int stage = 1; stage <= 2; stage++) {
+            if (profile_) HJR_TRY(hipEventRecord(prof_ev_[par][4 * s + 2 * (stage - 1)], stream_));
+            HJR_TRY(launch_stage(stream_, cfg_.dtype, stage, a, geff_));
+            if (profile_) HJR_TRY(hipEventRecord(prof_ev_[par][4 * s + 2 * (stage - 1) + 1], stream_));
+        }
+    }
+    HJR_TRY(launch_epilogue(stream_, args(par, 0)));
+    return HJR_OK;
+}
+
+hjr_status Engine::build_graph(int par, hipGraphExec_t* out)
+{
+    hipGraph_t g = nullptr;
+    HJR_TRY(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+    hjr_status st = enqueue_chunk_body(par);
+    hipError_t e = hipStreamEndCapture(stream_, &g);
+    if (st != HJR_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    HJR_TRY(e);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HJR_TRY(e);
+    return HJR_OK;
+}
+
+hjr_status Engine::step()
+{
+    if (table_dirty_) {
+        hjr_status st = upload_table();
+        if (st != HJR_OK) return st;
+    }
+    const int par = (int)(chunk_ & 1);
+    const int cap = cfg_.cap, K = cfg_.K;
+    Flight f;
+    f.chunk = chunk_;
+    f.job.assign(cap, nullptr);
+    f.limit.assign(cap, 0);
+    f.sched.assign(cap, 0);
+    ChunkHdr* hdr = (ChunkHdr*)h_ctl_[par];
+    ProbCtl* ctl = (ProbCtl*)(h_ctl_[par] + 256);
+    hdr->total_tiles = total_tiles_;
+    hdr->nprob = cap;
+    for (int s = 0; s < cap; s++) {
+        Job* j = slots_[s];
+        ctl[s].limit = 0;
+        ctl[s].fresh = 1;
+        if (j && !j->done && j->level_start_chunk <= chunk_) {
+            const int64_t left = cfg_.max_iter - j->sched;
+            const int lim = (int)std::max<int64_t>(0, std::min<int64_t>(K, left));
+            ctl[s].limit = lim;
+            ctl[s].fresh = j->fresh ? 1 : 0;
+            f.job[s] = j;
+            f.limit[s] = lim;
+            f.sched[s] = j->sched;
+            j->sched += lim;
+            j->fresh = false;
+        }
+    }
+    HJR_TRY(hipMemcpyAsync(d_hdr_[par], h_ctl_[par], ctl_bytes_, hipMemcpyHostToDevice, stream_));
+    // launch no more workgroups than there are tiles (a multiple of 8, so
+    // that every XCD gets its share)
+    geff_ = (int)std::min<int64_t>(grid_, std::max<int64_t>(8, (total_tiles_ + 7) / 8 * 8));
+    if (use_graph_) {
+        hipGraphExec_t ge = nullptr;
+        for (auto& g : graphs_[par])
+            if (g.first == geff_) ge = g.second;
+        if (!ge) {
+            hjr_status st = build_graph(par, &ge);
+            if (st != HJR_OK) return st;
+            graphs_[par].push_back({geff_, ge});
+        }
+        HJR_TRY(hipGraphLaunch(ge, stream_));
+    } else {
+        hjr_status st = enqueue_chunk_body(par);
+        if (st != HJR_OK) return st;
+    }
+    HJR_TRY(hipMemcpyAsync(h_compact_[par], d_compact_[par], sizeof(double) * (size_t)cap * K,
+                           hipMemcpyDeviceToHost, stream_));
+    HJR_TRY(hipEventCreateWithFlags(&f.ev, hipEventDisableTiming));
+    HJR_TRY(hipEventRecord(f.ev, stream_));
+    flights_.push_back(std::move(f));
+    chunk_++;
+    while ((int)flights_.size() > depth_) {
+        Flight g = std::move(flights_.front());
+        flights_.erase(flights_.begin());
+        hjr_status st = process(g);
+        if (st != HJR_OK) return st;
+    }
+    return HJR_OK;
+}
+
+hjr_status Engine::drain()
+{
+    while (!flights_.empty()) {
+        Flight g = std::move(flights_.front());
+        flights_.erase(flights_.begin());
+        hjr_status st = process(g);
+        if (st != HJR_OK) return st;
+    }
+    return HJR_OK;
+}
+
+hjr_status Engine::process(Flight& f)
+{
+    hipError_t e = hipEventSynchronize(f.ev);
+    (void)hipEventDestroy(f.ev);
+    f.ev = nullptr;
+    if (e != hipSuccess) {
+        last_err_ = e;
+        return HJR_EDEVICE;
+    }
+    const int par = (int)(f.chunk & 1);
+    const double* r = h_compact_[par];
+    const int K = cfg_.K;
+    if (profile_)
+        for (int s = 0; s < K; s++)
+            for (int st = 0; st < 2; st++) {
+                float ms = 0.f;
+                HJR_TRY(hipEventElapsedTime(&ms, prof_ev_[par][4 * s + 2 * st],
+                                            prof_ev_[par][4 * s + 2 * st + 1]));
+                prof_ms_[st] += ms;
+                prof_n_[st] += 1;
+            }
+    for (int s = 0; s < cfg_.cap; s++) {
+        Job* j = f.job[s];
+        const int lim = f.limit[s];
+        if (!j || j->done || lim == 0) continue;
+        if (j->slot != s || j->level_start_chunk > f.chunk) continue;  // stale results
+        const double* rs = r + (int64_t)s * K;
+        int hit = -1;
+        for (int k = 0; k < lim; k++)
+            if (rs[k] < j->tol) {
+                hit = k;
+                break;
+            }
+        if (hit >= 0) {
+            finish_level(j, HJR_OK, f.sched[s] + hit + 1, rs[hit]);
+        } else if (f.sched[s] + lim >= cfg_.max_iter) {
+            finish_level(j, HJR_NOT_CONVERGED, f.sched[s] + lim, rs[lim - 1]);
+        }
+    }
+    return HJR_OK;
+}
+
+void Engine::finish_level(Job* j, int status, int64_t iters, double residual)
+{
+    const int c = j->cur;
+    j->level_iters[c] = iters;
+    j->residual = residual;
+    const Level& L = j->lev[c];
+    if (L.mask) {
+        hipError_t e = launch_mask(stream_, cfg_.dtype, L.grid, L.V, L.mask,
+                                   d_mask_counts_ + 4 * (int64_t)j->slot + c);
+        if (e != hipSuccess) {
+            last_err_ = e;
+            status = HJR_EDEVICE;
+        }
+    }
+    if (status == HJR_OK && c + 1 < j->nlev) {
+        j->cur = c + 1;
+        if (setup_level(j) == HJR_OK) return;
+        status = HJR_EDEVICE;
+    }
+    j->status = status;
+    j->done = true;
+    slots_[j->slot] = nullptr;
+    // later chunks still in flight must not look at this job again (its
+    // owner may release it from on_done)
+    for (auto& f : flights_)
+        for (auto& q : f.job)
+            if (q == j) q = nullptr;
+    running_--;
+    table_dirty_ = true;
+    if (j->on_done) j->on_done(*j);
+}
+
+hjr_status Engine::read_state(int slot, ProbState* out)
+{
+    HJR_TRY(hipMemcpyAsync(out, d_state_ + slot, sizeof(ProbState), hipMemcpyDeviceToHost, stream_));
+    HJR_TRY(hipStreamSynchronize(stream_));
+    return HJR_OK;
+}
+
+hjr_status Engine::read_mask_counts(int slot, uint64_t* out4)
+{
+    HJR_TRY(hipMemcpyAsync(out4, d_mask_counts_ + 4 * (int64_t)slot, 4 * sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, stream_));
+    HJR_TRY(hipStreamSynchronize(stream_));
+    return HJR_OK;
+}
+
+}  // namespace hjr

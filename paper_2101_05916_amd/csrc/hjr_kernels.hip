@@ -1,0 +1,538 @@
+// hjr_kernels.hip -- CDNA4 (gfx950) kernels of libhjr.
+//
+// The hot path is the time-marched solve of the HJI variational inequality
+// (paper Sec. II-A, eq. (2)) with ENO2 upwind derivatives, global
+// Lax-Friedrichs dissipation and a two-stage TVD Runge-Kutta step, followed
+// by the projection V <- min(l, V).  Each RK stage is one sweep over the
+// grid; it is a memory-bound cross-shaped stencil (9 points in 2-D, 17 in
+// 4-D), so it runs on the vector ALUs with coalesced loads, not on MFMA.
+//
+// Work decomposition: every problem of a batch is cut into tiles of kTile
+// consecutive nodes; the tiles of all problems form one index space that a
+// fixed-size grid of workgroups strides through.  Workgroup b runs on XCD
+// b mod 8, and each XCD takes one contiguous eighth of the tile space, so
+// the planes a tile's stencil touches are mostly in that XCD's L2.
+//
+// Convergence is decided on the device: stage 2 max-reduces |V' - V| per
+// workgroup (wave shuffles, then LDS) and folds it into the problem's
+// residual word with one 64-bit atomic max on the IEEE bit pattern (a
+// non-negative double orders like its bits).  Every kernel of iteration s
+// first reads the residual of iteration s-1 and skips the problem if it is
+// already below tol, so a chunk of K iterations can be enqueued blind and
+// still stops at exactly the right step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "hjr_device.hpp"
+#include "hjr_launch.hpp"
+#include "hjr_stencil.hpp"
+
+namespace hjr {
+
+// ------------------------------------------------------------------------
+// small helpers
+// ------------------------------------------------------------------------
+
+__device__ __forceinline__ double bitsd(uint64_t b)
+{
+    return __longlong_as_double((long long)b);
+}
+
+// Max of a 64-bit value over the workgroup; result valid in every thread.
+template <int NB>
+__device__ uint64_t block_max_u64(uint64_t v, uint64_t* red)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        uint64_t o = __shfl_xor(v, off, 64);
+        v = umax64(v, o);
+    }
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    uint64_t r = red[0];
+#pragma unroll
+    for (int i = 1; i < NB / 64; i++) r = umax64(r, red[i]);
+    return r;
+}
+
+// Problem owning global tile t: the last p with tile_begin <= t (binary
+// search; tile_begin is non-decreasing over the table, and a problem without
+// tiles shares its tile_begin with the next one, which therefore wins).
+__device__ __forceinline__ int find_prob(const ProbDesc* probs, int nprob, int64_t t)
+{
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].tile_begin <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool prob_active(const ChunkArgs& A, int p)
+{
+    if (A.slot >= A.ctl[p].limit) return false;
+    uint64_t r = 0;
+#pragma unroll
+    for (int s = 0; s < kResSubs; s++) r = umax64(r, A.res[res_index(p, A.slot, s, A.K)]);
+    return !(bitsd(r) < A.probs[p].tol);
+}
+
+// Fold a workgroup's max |V' - V| into problem p's residual of this step.
+// The residual is spread over kResSubs words (the reader takes their max),
+// and the atomic is skipped when the word already holds at least this value
+// -- the words only grow, so a stale read can only cause a redundant
+// atomic, never a lost one.  Few workgroups beat the running max, so the
+// device-scope atomics on any one word stay few.
+template <int NB>
+__device__ __forceinline__ void flush_residual(const ChunkArgs& A, int p, uint64_t rmax, uint64_t* red)
+{
+    const uint64_t r = block_max_u64<NB>(rmax, red);
+    if (threadIdx.x == 0) {
+        unsigned long long* w =
+            (unsigned long long*)&A.res[res_index(p, A.slot + 1, blockIdx.x % kResSubs, A.K)];
+        const unsigned long long seen = __atomic_load_n(w, __ATOMIC_RELAXED);
+        if (r > seen) atomicMax(w, (unsigned long long)r);
+    }
+}
+
+template <typename T, int STAGE>
+__global__ __launch_bounds__(kStageBlock) void k_stage(ChunkArgs A)
+{
+    __shared__ uint64_t red[kStageBlock / 64];
+    __shared__ __align__(16) char smem[kPlaneElems * sizeof(T)];
+    T* lds = (T*)smem;
+    const int64_t total = A.hdr->total_tiles;
+    const int nprob = A.hdr->nprob;
+    const int G8 = (int)gridDim.x >> 3;
+    const int xcd = (int)blockIdx.x & 7;
+    const int local = (int)blockIdx.x >> 3;
+    const int64_t beg = total * xcd / 8, end = total * (xcd + 1) / 8;
+    int cur = -1;
+    bool active = false;
+    uint64_t rmax = 0;
+    for (int64_t t = beg + local; t < end; t += G8) {
+        const int p = find_prob(A.probs, nprob, t);
+        if (p != cur) {
+            if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red);
+            cur = p;
+            rmax = 0;
+            active = prob_active(A, p);
+        }
+        if (!active) continue;
+        const ProbDesc& P = A.probs[p];
+        rmax = umax64(rmax, run_tile<T, STAGE>(P, A.states[p], t - P.tile_begin, lds));
+    }
+    if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red);
+}
+
+// Chunk prologue: one workgroup per problem slot.  Slot 0 of the residual
+// buffer receives the carried-in residual (+inf on the first chunk of a
+// level, else the last residual of the previous chunk); slots 1..K are
+// cleared for this chunk's atomics.
+__global__ __launch_bounds__(64) void k_prologue(ChunkArgs A)
+{
+    const int p = blockIdx.x;
+    if (p >= A.hdr->nprob) return;
+    const uint64_t inf_bits = 0x7ff0000000000000ull;
+    const uint64_t carried =
+        A.ctl[p].fresh ? inf_bits : dbits(A.prev[(int64_t)p * A.K + (A.K - 1)]);
+    const int64_t n = (int64_t)(A.K + 1) * kResSubs;
+    uint64_t* r = A.res + (int64_t)p * n;
+    for (int64_t e = threadIdx.x; e < n; e += blockDim.x) r[e] = (e == 0) ? carried : 0ull;
+}
+
+// Chunk epilogue: reduce the kResSubs words of every iteration.
+__global__ __launch_bounds__(64) void k_epilogue(ChunkArgs A)
+{
+    const int p = blockIdx.x;
+    if (p >= A.hdr->nprob) return;
+    for (int s = threadIdx.x; s < A.K; s += blockDim.x) {
+        uint64_t r = 0;
+        for (int k = 0; k < kResSubs; k++) r = umax64(r, A.res[res_index(p, s + 1, k, A.K)]);
+        A.compact[(int64_t)p * A.K + s] = bitsd(r);
+    }
+}
+
+// ------------------------------------------------------------------------
+// per-level set-up: Lax-Friedrichs bounds, dt, lookup table
+// ------------------------------------------------------------------------
+
+// f_i at node x for control vertex vu and disturbance vertex vd, in double.
+__device__ void dyn_f(const ProbDesc& P, const double* x, int vu, int vd, double* f)
+{
+    const double* p = P.par;
+    switch (P.kind) {
+    case HJR_QUAD_Z2D: {
+        const double u = (vu & 1) ? p[3] : p[2];
+        const double d = (vd & 1) ? P.dhi[0] : P.dlo[0];
+        f[0] = x[1];
+        f[1] = p[0] * u - p[1] + d;
+        break;
+    }
+    case HJR_QUAD_X4D: {
+        const double S = (vu & 1) ? p[4] : -p[4];
+        const double d = (vd & 1) ? P.dhi[0] : P.dlo[0];
+        f[0] = x[1] + d;
+        f[1] = p[0] * tan(x[2]);
+        f[2] = -p[1] * x[2] + x[3];
+        f[3] = -p[2] * x[2] + p[3] * S;
+        break;
+    }
+    case HJR_DI2X2: {
+        const int za = (int)p[8], va = (int)p[9], zb = (int)p[10], vb = (int)p[11];
+        const double ua = (vu & 1) ? p[3] : p[2];
+        const double ub = (vu & 2) ? p[7] : p[6];
+        const double da = (vd & 1) ? P.dhi[0] : P.dlo[0];
+        const double db = (vd & 2) ? P.dhi[1] : P.dlo[1];
+        f[za] = x[va];
+        f[va] = p[0] * ua - p[1] + da;
+        f[zb] = x[vb];
+        f[vb] = p[4] * ub - p[5] + db;
+        break;
+    }
+    default:
+        f[0] = f[1] = f[2] = f[3] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_alpha(ProbDesc P, ProbState* st)
+{
+    __shared__ uint64_t red[kBlock / 64];
+    const int D = P.ndim;
+    const int nu = (P.kind == HJR_DI2X2) ? 4 : 2;
+    const int nd = (P.kind == HJR_DI2X2) ? 4 : 2;
+    uint64_t m[4] = {0, 0, 0, 0};
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < P.N;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        double x[4] = {0, 0, 0, 0};
+        int64_t q = idx;
+        for (int a = D - 1; a >= 0; a--) {
+            const int j = (int)(q % P.n[a]);
+            q /= P.n[a];
+            x[a] = P.lo[a] + (double)j * P.h[a];
+        }
+        for (int vu = 0; vu < nu; vu++)
+            for (int vd = 0; vd < nd; vd++) {
+                double f[4] = {0, 0, 0, 0};
+                dyn_f(P, x, vu, vd, f);
+                for (int a = 0; a < D; a++) m[a] = umax64(m[a], dbits(fabs(f[a])));
+            }
+    }
+    for (int a = 0; a < D; a++) {
+        const uint64_t r = block_max_u64<kBlock>(m[a], red);
+        if (threadIdx.x == 0) atomicMax((unsigned long long*)&st->alpha_bits[a], (unsigned long long)r);
+    }
+}
+
+// dt = cfl / sum_a alpha_a / h_a, the Lax-Friedrichs coefficients
+// alpha_a * 0.5 / h_a in both precisions, and for QUAD_X4D the table
+// g tan(theta_j) * 0.5 / h_1 over the nodes of axis 2.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_finalize(ProbDesc P, ProbState* st)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double s = 0.0;
+        for (int a = 0; a < 4; a++) {
+            const double al = a < P.ndim ? bitsd(st->alpha_bits[a]) : 0.0;
+            st->alpha[a] = al;
+            if (a < P.ndim) s += al / P.h[a];
+            st->ah[a] = a < P.ndim ? al * P.hih[a] : 0.0;
+            st->ah_f[a] = (float)st->ah[a];
+        }
+        st->dt = P.cfl / s;
+        st->dt_f = (float)st->dt;
+    }
+    if (P.kind == HJR_QUAD_X4D && P.table) {
+        T* tab = (T*)P.table;
+        for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < P.n[2]; j += gridDim.x * blockDim.x)
+            tab[j] = (T)(P.par[0] * tan(P.lo[2] + (double)j * P.h[2]) * P.hih[1]);
+    }
+}
+
+__global__ void k_zero_state(ProbState* st)
+{
+    if (threadIdx.x < 4) st->alpha_bits[threadIdx.x] = 0;
+    if (threadIdx.x == 0) st->mask_count = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init(T* V, const T* l, const T* V0, int64_t N)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T lv = l[i];
+        if (V0) {
+            const T v0 = V0[i];
+            V[i] = (lv < v0) ? lv : v0;
+        } else {
+            V[i] = lv;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u64(uint64_t* p, int64_t n, uint64_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------------------
+// level transition and refinement mask
+// ------------------------------------------------------------------------
+
+struct InterpArgs {
+    int D;
+    int ns[4];
+    int nd[4];
+    int64_t ss[4];  // source strides
+    int64_t Nd;
+};
+
+// Multilinear sample of the source grid at every destination node: integer
+// cell index and FP64 weight per axis, corners summed in row-major order of
+// their offsets in FP64 without fused multiply-adds, one rounding at the end.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_interp(InterpArgs A, const T* __restrict__ Vs,
+                                                   T* __restrict__ Vd, const T* __restrict__ ld)
+{
+#pragma clang fp contract(off)
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < A.Nd;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t q[4] = {0, 0, 0, 0};
+        double t[4] = {0, 0, 0, 0};
+        int64_t rest = idx;
+        for (int a = A.D - 1; a >= 0; a--) {
+            const int64_t j = rest % A.nd[a];
+            rest /= A.nd[a];
+            const int64_t num = j * (int64_t)(A.ns[a] - 1);
+            int64_t qa = num / (A.nd[a] - 1);
+            const int64_t r = num % (A.nd[a] - 1);
+            if (qa == A.ns[a] - 1) {
+                qa = A.ns[a] - 2;
+                t[a] = 1.0;
+            } else {
+                t[a] = (double)r / (double)(A.nd[a] - 1);
+            }
+            q[a] = qa;
+        }
+        double acc = 0.0;
+        const int nc = 1 << A.D;
+        for (int c = 0; c < nc; c++) {
+            double w = 1.0;
+            int64_t off = 0;
+            for (int a = 0; a < A.D; a++) {
+                const int ca = (c >> (A.D - 1 - a)) & 1;
+                w = w * (ca ? t[a] : 1.0 - t[a]);
+                off += (q[a] + ca) * A.ss[a];
+            }
+            acc = acc + w * (double)Vs[off];
+        }
+        T v = (T)acc;
+        if (ld) {
+            const T lv = ld[idx];
+            v = (lv < v) ? lv : v;
+        }
+        Vd[idx] = v;
+    }
+}
+
+struct MaskArgs {
+    int D;
+    int nc[4];      // cells per axis (n - 1)
+    int64_t s[4];   // node strides
+    int64_t Nc;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mask(MaskArgs A, const T* __restrict__ V,
+                                                 uint8_t* __restrict__ mask, uint64_t* counter)
+{
+    __shared__ uint64_t red[kBlock / 64];
+    uint64_t cnt = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // every thread runs the same number of loop trips so the block reduction
+    // below is reached uniformly
+    const int64_t trips = (A.Nc + stride - 1) / stride;
+    for (int64_t k = 0; k < trips; k++) {
+        const int64_t c = start + k * stride;
+        if (c < A.Nc) {
+            int64_t base = 0, rest = c;
+            for (int a = A.D - 1; a >= 0; a--) {
+                base += (rest % A.nc[a]) * A.s[a];
+                rest /= A.nc[a];
+            }
+            bool pos = false, neg = false;
+            for (int k2 = 0; k2 < (1 << A.D); k2++) {
+                int64_t off = base;
+                for (int a = 0; a < A.D; a++) off += ((k2 >> a) & 1) * A.s[a];
+                const T v = V[off];
+                pos = pos || (v >= T(0));
+                neg = neg || (v < T(0));
+            }
+            const uint8_t m = (pos && neg) ? 1 : 0;
+            mask[c] = m;
+            cnt += m;
+        }
+    }
+    // sum over the block via the max-reduction helper's shuffle pattern
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t s = 0;
+        for (int i = 0; i < kBlock / 64; i++) s += red[i];
+        if (s && counter) atomicAdd((unsigned long long*)counter, (unsigned long long)s);
+    }
+}
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+
+static int grid_for(int64_t n, int cap)
+{
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_prologue(hipStream_t s, const ChunkArgs& a)
+{
+    hipLaunchKernelGGL(k_prologue, dim3(a.cap), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_epilogue(hipStream_t s, const ChunkArgs& a)
+{
+    hipLaunchKernelGGL(k_epilogue, dim3(a.cap), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage(hipStream_t s, int dtype, int stage, const ChunkArgs& a, int grid)
+{
+    if (dtype == HJR_F32) {
+        if (stage == 1)
+            hipLaunchKernelGGL((k_stage<float, 1>), dim3(grid), dim3(kStageBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_stage<float, 2>), dim3(grid), dim3(kStageBlock), 0, s, a);
+    } else {
+        if (stage == 1)
+            hipLaunchKernelGGL((k_stage<double, 1>), dim3(grid), dim3(kStageBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_stage<double, 2>), dim3(grid), dim3(kStageBlock), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_level_setup(hipStream_t s, int dtype, const ProbDesc& P, ProbState* st)
+{
+    hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, s, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_alpha, dim3(grid_for(P.N, 1024)), dim3(kBlock), 0, s, P, st);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int g = grid_for(P.ndim >= 3 ? P.n[2] : 1, 64);
+    if (dtype == HJR_F32)
+        hipLaunchKernelGGL((k_finalize<float>), dim3(g), dim3(kBlock), 0, s, P, st);
+    else
+        hipLaunchKernelGGL((k_finalize<double>), dim3(g), dim3(kBlock), 0, s, P, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(hipStream_t s, int dtype, void* V, const void* l, const void* V0,
+                       int64_t N)
+{
+    const int g = grid_for(N, 4096);
+    if (dtype == HJR_F32)
+        hipLaunchKernelGGL((k_init<float>), dim3(g), dim3(kBlock), 0, s, (float*)V,
+                           (const float*)l, (const float*)V0, N);
+    else
+        hipLaunchKernelGGL((k_init<double>), dim3(g), dim3(kBlock), 0, s, (double*)V,
+                           (const double*)l, (const double*)V0, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_interp(hipStream_t s, int dtype, const hjr_grid& src, const void* Vs,
+                         const hjr_grid& dst, void* Vd, const void* l_dst)
+{
+    InterpArgs A;
+    A.D = src.ndim;
+    A.Nd = 1;
+    for (int a = 0; a < 4; a++) {
+        A.ns[a] = a < A.D ? src.n[a] : 1;
+        A.nd[a] = a < A.D ? dst.n[a] : 1;
+        A.ss[a] = 0;
+    }
+    int64_t st = 1;
+    for (int a = A.D - 1; a >= 0; a--) {
+        A.ss[a] = st;
+        st *= src.n[a];
+        A.Nd *= dst.n[a];
+    }
+    const int g = grid_for(A.Nd, 8192);
+    if (dtype == HJR_F32)
+        hipLaunchKernelGGL((k_interp<float>), dim3(g), dim3(kBlock), 0, s, A, (const float*)Vs,
+                           (float*)Vd, (const float*)l_dst);
+    else
+        hipLaunchKernelGGL((k_interp<double>), dim3(g), dim3(kBlock), 0, s, A, (const double*)Vs,
+                           (double*)Vd, (const double*)l_dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask(hipStream_t s, int dtype, const hjr_grid& g, const void* V,
+                       uint8_t* mask, uint64_t* counter)
+{
+    MaskArgs A;
+    A.D = g.ndim;
+    A.Nc = 1;
+    int64_t st = 1;
+    for (int a = 3; a >= 0; a--) {
+        A.nc[a] = a < A.D ? g.n[a] - 1 : 1;
+        A.s[a] = 0;
+    }
+    for (int a = A.D - 1; a >= 0; a--) {
+        A.s[a] = st;
+        st *= g.n[a];
+        A.Nc *= (g.n[a] - 1);
+    }
+    const int gr = grid_for(A.Nc, 8192);
+    if (dtype == HJR_F32)
+        hipLaunchKernelGGL((k_mask<float>), dim3(gr), dim3(kBlock), 0, s, A, (const float*)V, mask,
+                           counter);
+    else
+        hipLaunchKernelGGL((k_mask<double>), dim3(gr), dim3(kBlock), 0, s, A, (const double*)V, mask,
+                           counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(hipStream_t s, uint64_t* p, int64_t n, uint64_t value)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 1024)), dim3(kBlock), 0, s, p, n, value);
+    return hipGetLastError();
+}
+
+int stage_blocks_per_cu(int dtype)
+{
+    int n = 0;
+    hipError_t e;
+    if (dtype == HJR_F32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_stage<float, 2>, kStageBlock, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_stage<double, 2>, kStageBlock, 0);
+    if (e != hipSuccess || n < 1) n = 2;
+    return n;
+}
+
+}  // namespace hjr

@@ -1,0 +1,38 @@
+// hjr_launch.hpp -- host-side launchers of the libhjr HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/hjr.h"
+#include "hjr_device.hpp"
+
+namespace hjr {
+
+// Iteration kernels (one chunk = prologue, K x (stage 1, stage 2), epilogue).
+hipError_t launch_prologue(hipStream_t s, const ChunkArgs& a);
+hipError_t launch_stage(hipStream_t s, int dtype, int stage, const ChunkArgs& a, int grid);
+hipError_t launch_epilogue(hipStream_t s, const ChunkArgs& a);
+
+// Per-level set-up of one problem: Lax-Friedrichs bounds, time step and
+// lookup table, written to *st.
+hipError_t launch_level_setup(hipStream_t s, int dtype, const ProbDesc& P, ProbState* st);
+
+// V = l (V0 == NULL) or V = min(l, V0); V0 may equal V.
+hipError_t launch_init(hipStream_t s, int dtype, void* V, const void* l, const void* V0,
+                       int64_t N);
+
+// Multilinear transfer between two grids over the same box (see hjr_interp).
+hipError_t launch_interp(hipStream_t s, int dtype, const hjr_grid& src, const void* Vs,
+                         const hjr_grid& dst, void* Vd, const void* l_dst);
+
+// Straddle mask of a level; adds the number of marked cells to *counter.
+hipError_t launch_mask(hipStream_t s, int dtype, const hjr_grid& g, const void* V,
+                       uint8_t* mask, uint64_t* counter);
+
+// Fill n 64-bit words with value.
+hipError_t launch_fill_u64(hipStream_t s, uint64_t* p, int64_t n, uint64_t value);
+
+// Workgroups of the iteration kernel that fit on one compute unit.
+int stage_blocks_per_cu(int dtype);
+
+}  // namespace hjr

@@ -1,0 +1,529 @@
+// hjr_stencil.hpp -- device side of one RK stage: the upwind derivatives,
+// the Hamiltonians and the two tile shapes of the stage kernels.
+//
+// Notation.  Along an axis of spacing h, w0..w4 are the values at
+// j-2..j+2 (ghost values past the ends are linear extrapolations of the two
+// end nodes).  With raw differences a..d (h times the first divided
+// differences at j-3/2..j+3/2) and raw second differences sm, s0, sp,
+//     h D^- = b + cm/2,  h D^+ = c - cp/2,
+// cm / cp being the second difference of smaller magnitude on each side (a
+// tie takes the outer one).  A stage needs only
+//     sum = h (D^+ + D^-)   and   dif = h (D^+ - D^-)
+// per axis: the Hamiltonian is evaluated at p = sum * (0.5/h) and the
+// Lax-Friedrichs term is alpha * (0.5/h) * dif.  The 0.5/h factors are
+// folded into per-problem constants (ProbDesc::hc), so the Hamiltonians
+// below take `sum` directly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/hjr.h"
+#include "hjr_device.hpp"
+
+namespace hjr {
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f)
+{
+    return __umulhi(x, f.m) >> f.s;
+}
+
+template <typename T>
+struct Prec;
+template <>
+struct Prec<float> {
+    __device__ static const float* hih(const ProbDesc& P) { return P.hih_f; }
+    __device__ static const float* lo(const ProbDesc& P) { return P.lo_f; }
+    __device__ static const float* h(const ProbDesc& P) { return P.h_f; }
+    __device__ static const float* hc(const ProbDesc& P) { return P.hc_f; }
+    __device__ static const float* ah(const ProbState& S) { return S.ah_f; }
+    __device__ static float dt(const ProbState& S) { return S.dt_f; }
+};
+template <>
+struct Prec<double> {
+    __device__ static const double* hih(const ProbDesc& P) { return P.hih; }
+    __device__ static const double* lo(const ProbDesc& P) { return P.lo; }
+    __device__ static const double* h(const ProbDesc& P) { return P.h; }
+    __device__ static const double* hc(const ProbDesc& P) { return P.hc_d; }
+    __device__ static const double* ah(const ProbState& S) { return S.ah; }
+    __device__ static double dt(const ProbState& S) { return S.dt; }
+};
+
+// sum and dif of one axis from its five samples (see the header comment).
+template <typename T>
+__device__ __forceinline__ void eno_sum_dif(T w0, T w1, T w2, T w3, T w4, int order, T& sum, T& dif)
+{
+    const T a = w1 - w0, b = w2 - w1, c = w3 - w2, d = w4 - w3;
+    T pm = b, pp = c;
+    if (order != 1) {
+        const T sm = b - a, s0 = c - b, sp = d - c;
+        const T cm = (fabs(sm) <= fabs(s0)) ? sm : s0;
+        const T cp = (fabs(sp) <= fabs(s0)) ? sp : s0;
+        pm = b + T(0.5) * cm;
+        pp = c - T(0.5) * cp;
+    }
+    sum = pp + pm;
+    dif = pp - pm;
+}
+
+// Replace the samples of positions outside [0, n-1] by the linear
+// extrapolation of the two end nodes: v[-1] = 2v[0]-v[1], v[-2] = 3v[0]-2v[1]
+// and mirrored at the top.  m2, m1, p1, p2 hold loads from clamped (in-range)
+// positions; only loaded values feed the formulas (n >= 3).
+template <typename T>
+__device__ __forceinline__ void ghost_fix(int j, int n, T c, T& m2, T& m1, T& p1, T& p2)
+{
+    const bool lo1 = j >= 1, lo2 = j >= 2, hi1 = j <= n - 2, hi2 = j <= n - 3;
+    const T m1f = lo1 ? m1 : T(2) * c - p1;
+    const T p1f = hi1 ? p1 : T(2) * c - m1;
+    const T m2f = lo2 ? m2 : (lo1 ? T(2) * m1 - c : T(3) * c - T(2) * p1);
+    const T p2f = hi2 ? p2 : (hi1 ? T(2) * p1 - c : T(3) * c - T(2) * m1);
+    m2 = m2f;
+    m1 = m1f;
+    p1 = p1f;
+    p2 = p2f;
+}
+
+// Load through a uniform base pointer and a 32-bit element offset.
+template <typename T>
+__device__ __forceinline__ T ldg(const T* base, uint32_t i)
+{
+    return *(const T*)((const char*)base + (size_t)i * sizeof(T));
+}
+
+// Samples of one axis through a global array at element gi, for a position
+// j along that axis that is the same in the whole workgroup (uniform), so
+// the boundary test is a scalar branch.
+template <typename T>
+__device__ __forceinline__ void axis_global_uniform(const T* __restrict__ in, uint32_t gi, int j,
+                                                    int n, int s, T c, T& w0, T& w1, T& w3, T& w4)
+{
+    if (j >= 2 && j <= n - 3) {
+        w0 = ldg(in - 2 * s, gi);
+        w1 = ldg(in - s, gi);
+        w3 = ldg(in + s, gi);
+        w4 = ldg(in + 2 * s, gi);
+    } else {
+        const int om2 = j >= 2 ? 2 * s : (j >= 1 ? s : 0);
+        const int om1 = j >= 1 ? s : 0;
+        const int op1 = j <= n - 2 ? s : 0;
+        const int op2 = j <= n - 3 ? 2 * s : (j <= n - 2 ? s : 0);
+        w0 = ldg(in - om2, gi);
+        w1 = ldg(in - om1, gi);
+        w3 = ldg(in + op1, gi);
+        w4 = ldg(in + op2, gi);
+        ghost_fix<T>(j, n, c, w0, w1, w3, w4);
+    }
+}
+
+// ------------------------------------------------------------------------
+// Hamiltonians H(x, p) = max_u min_d p . f(x, u, d) of the affine models,
+// evaluated from per-axis sums (p_a = sum_a * 0.5/h_a) and node indices.
+// Over a box, an affine function's max/min sit at vertices, so each control
+// or disturbance term is a product with the coefficient picked by the sign
+// of its p component.  ProbDesc::hc holds the folded constants, written by
+// the host (fill_desc).
+// ------------------------------------------------------------------------
+
+// z' = vz, vz' = k u - g + d.  hc = {hih0*lo1, hih0*h1, Cpos, Cneg} with
+// Cpos = (max(k u) + min(d) - g) hih1, Cneg = (min(k u) + max(d) - g) hih1.
+template <typename T>
+struct HamZ2D {
+    T c0, c1, cpos, cneg;
+    __device__ void init(const ProbDesc& P)
+    {
+        const T* hc = Prec<T>::hc(P);
+        c0 = hc[0];
+        c1 = hc[1];
+        cpos = hc[2];
+        cneg = hc[3];
+    }
+    __device__ __forceinline__ T operator()(const T* sum, int j0, int j1, int j2, int j3) const
+    {
+        const T vzh = c0 + (T)j1 * c1;  // (0.5/h0) vz
+        return sum[0] * vzh + sum[1] * (sum[1] >= T(0) ? cpos : cneg);
+    }
+};
+
+// x' = vx + d, vx' = g tan(theta), theta' = -d1 theta + omega,
+// omega' = -d0 theta + n0 S.  hc = {hih0*lo1, hih0*h1, dlo*hih0, dhi*hih0,
+// hih2*(lo3 - d1 lo2), hih2*h3, hih2*d1*h2, d0*hih3*lo2, d0*hih3*h2,
+// n0*smax*hih3}; table[j2] = g tan(theta_j2) * hih1.
+template <typename T>
+struct HamX4D {
+    T c0, c1, dl, dh, A, B, C, D, E, n0s;
+    const T* gts;
+    __device__ void init(const ProbDesc& P)
+    {
+        const T* hc = Prec<T>::hc(P);
+        c0 = hc[0];
+        c1 = hc[1];
+        dl = hc[2];
+        dh = hc[3];
+        A = hc[4];
+        B = hc[5];
+        C = hc[6];
+        D = hc[7];
+        E = hc[8];
+        n0s = hc[9];
+        gts = (const T*)P.table;
+    }
+    __device__ __forceinline__ T operator()(const T* sum, int j0, int j1, int j2, int j3) const
+    {
+        const T cvx = c0 + (T)j1 * c1;                   // (0.5/h0) vx
+        const T tw = A + (T)j3 * B - (T)j2 * C;          // (0.5/h2)(omega - d1 theta)
+        const T t3 = D + (T)j2 * E;                      // (0.5/h3) d0 theta
+        const T s0 = sum[0];
+        return s0 * (cvx + (s0 >= T(0) ? dl : dh)) + sum[1] * gts[j2] + sum[2] * tw -
+               sum[3] * t3 + n0s * fabs(sum[3]);
+    }
+};
+
+// Two independent vertical models on a permutation of the axes (test model).
+template <typename T>
+struct HamDI2X2 {
+    int za, va, zb, vb;
+    T ga, kalo, kahi, dalo, dahi, gb, kblo, kbhi, dblo, dbhi;
+    T hih[4], lo[4], h[4];
+    __device__ void init(const ProbDesc& P)
+    {
+        ga = (T)P.par[1];
+        kalo = (T)(P.par[0] * P.par[2]);
+        kahi = (T)(P.par[0] * P.par[3]);
+        gb = (T)P.par[5];
+        kblo = (T)(P.par[4] * P.par[6]);
+        kbhi = (T)(P.par[4] * P.par[7]);
+        za = (int)P.par[8];
+        va = (int)P.par[9];
+        zb = (int)P.par[10];
+        vb = (int)P.par[11];
+        dalo = (T)P.dlo[0];
+        dahi = (T)P.dhi[0];
+        dblo = (T)P.dlo[1];
+        dbhi = (T)P.dhi[1];
+        for (int a = 0; a < 4; a++) {
+            hih[a] = Prec<T>::hih(P)[a];
+            lo[a] = Prec<T>::lo(P)[a];
+            h[a] = Prec<T>::h(P)[a];
+        }
+    }
+    __device__ static T pick(const T* v, int i)
+    {
+        return i == 0 ? v[0] : (i == 1 ? v[1] : (i == 2 ? v[2] : v[3]));
+    }
+    __device__ __forceinline__ T operator()(const T* sum, int j0, int j1, int j2, int j3) const
+    {
+        const int jj[4] = {j0, j1, j2, j3};
+        T p[4], x[4];
+        for (int a = 0; a < 4; a++) {
+            p[a] = sum[a] * hih[a];
+            x[a] = lo[a] + (T)jj[a] * h[a];
+        }
+        const T pva = pick(p, va), pvb = pick(p, vb);
+        return pick(p, za) * pick(x, va) - ga * pva + fmax(kalo * pva, kahi * pva) +
+               fmin(dalo * pva, dahi * pva) + pick(p, zb) * pick(x, vb) - gb * pvb +
+               fmax(kblo * pvb, kbhi * pvb) + fmin(dblo * pvb, dbhi * pvb);
+    }
+};
+
+// ------------------------------------------------------------------------
+// stage epilogue
+// ------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t dbits(double x)
+{
+    return (uint64_t)__double_as_longlong(x);
+}
+
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b)
+{
+    return a > b ? a : b;
+}
+
+// Stage 1 writes Vhat = c + dt L.  Stage 2 writes V' = min(l, (V + c + dt L)/2)
+// over V and folds |V' - V| (in double) into rmax.
+template <typename T, int STAGE>
+__device__ __forceinline__ void finish_node(const ProbDesc& P, uint32_t gi, T c, T L, T dt,
+                                            uint64_t& rmax)
+{
+    if (STAGE == 1) {
+        *(T*)((char*)P.Vhat + (size_t)gi * sizeof(T)) = c + dt * L;
+    } else {
+        T* vp = (T*)((char*)P.V + (size_t)gi * sizeof(T));
+        const T vt = c + dt * L;
+        const T vo = *vp;
+        const T avg = T(0.5) * (vo + vt);
+        const T lv = ldg((const T*)P.l, gi);
+        const T vn = (lv < avg) ? lv : avg;
+        *vp = vn;
+        rmax = umax64(rmax, dbits(fabs((double)vn - (double)vo)));
+    }
+}
+
+// ------------------------------------------------------------------------
+// flat tiles: kTile consecutive nodes, any shape (fallback path)
+// ------------------------------------------------------------------------
+
+template <typename T, int D, class Ham, int STAGE>
+__device__ uint64_t tile_flat(const ProbDesc& P, const ProbState& S, int64_t tile)
+{
+    Ham ham;
+    ham.init(P);
+    const T* ah = Prec<T>::ah(S);
+    const T dt = Prec<T>::dt(S);
+    const int order = P.order;
+    const int N = (int)P.N;
+    const T* __restrict__ in = (const T*)(STAGE == 1 ? P.V : P.Vhat);
+    uint64_t rmax = 0;
+    const int base = (int)(tile * kTile) + (int)threadIdx.x;
+    for (int k = 0; k < kNodesPerThread; k++) {
+        const int idx = base + k * kStageBlock;
+        if (idx >= N) break;
+        int j[4] = {0, 0, 0, 0};
+        uint32_t q = (uint32_t)idx;
+#pragma unroll
+        for (int a = D - 1; a >= 1; a--) {
+            const uint32_t qq = fdiv(q, P.div[a]);
+            j[a] = (int)(q - qq * (uint32_t)P.n[a]);
+            q = qq;
+        }
+        j[0] = (int)q;
+        const T c = in[idx];
+        T sum[4] = {0, 0, 0, 0};
+        T L = T(0);
+#pragma unroll
+        for (int a = 0; a < D; a++) {
+            const int s = (int)P.stride[a], n = P.n[a];
+            T m2 = in[idx - (j[a] >= 2 ? 2 * s : (j[a] >= 1 ? s : 0))];
+            T m1 = in[idx - (j[a] >= 1 ? s : 0)];
+            T p1 = in[idx + (j[a] <= n - 2 ? s : 0)];
+            T p2 = in[idx + (j[a] <= n - 3 ? 2 * s : (j[a] <= n - 2 ? s : 0))];
+            ghost_fix<T>(j[a], n, c, m2, m1, p1, p2);
+            T dif;
+            eno_sum_dif<T>(m2, m1, c, p1, p2, order, sum[a], dif);
+            L += ah[a] * dif;
+        }
+        if (D == 2)
+            L += ham(sum, j[0], j[1], 0, 0);
+        else
+            L += ham(sum, j[0], j[1], j[2], j[3]);
+        finish_node<T, STAGE>(P, (uint32_t)idx, c, L, dt, rmax);
+    }
+    return rmax;
+}
+
+// ------------------------------------------------------------------------
+// plane tiles: rows of the two fastest axes staged in LDS with ghosts
+// ------------------------------------------------------------------------
+
+// Load / store through a uniform base pointer and a 32-bit byte offset
+// (the host keeps N * sizeof(T) < 2^32 for plane tiles), so the address is
+// one SGPR pair plus one VGPR and costs no 64-bit vector arithmetic.
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, uint32_t i)
+{
+    return *(const T*)((const char*)base + i * (uint32_t)sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ void st32(T* base, uint32_t i, T v)
+{
+    *(T*)((char*)base + i * (uint32_t)sizeof(T)) = v;
+}
+
+// Clamped offsets of the samples j-2, j-1, j+1, j+2 along an axis of stride
+// s and length n (out-of-range samples read the centre; ghost_fix replaces
+// them afterwards).
+__device__ __forceinline__ void clamped_offsets(int j, int n, int s, int* o)
+{
+    o[0] = j >= 2 ? -2 * s : (j >= 1 ? -s : 0);
+    o[1] = j >= 1 ? -s : 0;
+    o[2] = j <= n - 2 ? s : 0;
+    o[3] = j <= n - 3 ? 2 * s : (j <= n - 2 ? s : 0);
+}
+
+// Tile t of a problem covers rows [r0, r1) of axis D-2 at a fixed index of
+// the outer axes (i0, i1 for D = 4); the host keeps (r1 - r0) * n_last <=
+// kPlaneNodesPT * kStageBlock.  The rows r0-2 .. r1+1 of the LDS block are
+// loaded in one batch; the outer-axis neighbours (and in stage 2, V and l)
+// of the nodes are loaded two nodes at a time.  The LDS block has columns -2 .. n_last+1 (stride RS);
+// out-of-range rows and columns hold the ghost extrapolations, so every
+// in-plane neighbour is a constant LDS offset.
+template <typename T, int D, class Ham, int STAGE, int RS>
+__device__ uint64_t tile_plane(const ProbDesc& P, const ProbState& S, int64_t tile, T* lds)
+{
+    const T* __restrict__ in = (const T*)(STAGE == 1 ? P.V : P.Vhat);
+    const int ra = D - 2, ca = D - 1;  // row axis, column axis
+    const int nr = P.n[ra], nc = P.n[ca];
+    const int chunk = (int)(tile % P.chunks);
+    const int outer = (int)(tile / P.chunks);
+    int i0 = 0, i1 = 0;
+    if (D == 4) {
+        i1 = outer % P.n[1];
+        i0 = outer / P.n[1];
+    }
+    const int r0 = chunk * P.rows;
+    const int r1 = min(r0 + P.rows, nr);
+    const uint32_t plane0 = (uint32_t)outer * (uint32_t)(nr * nc);
+    const int lr0 = max(r0 - 2, 0), lr1 = min(r1 + 2, nr);
+    const int nload = (lr1 - lr0) * nc;
+    const uint32_t load0 = plane0 + (uint32_t)(lr0 * nc);  // the loaded rows are contiguous
+    const int cnt = (r1 - r0) * nc;
+    const uint32_t node0 = plane0 + (uint32_t)(r0 * nc);
+    const int tid = threadIdx.x;
+
+    // ---- every global load of the tile ----
+    T sv[kPlaneStagePT];
+#pragma unroll
+    for (int k = 0; k < kPlaneStagePT; k++) {
+        const int e = tid + k * kStageBlock;
+        sv[k] = (e < nload) ? ld32(in, load0 + (uint32_t)e) : T(0);
+    }
+    int o0[4] = {0, 0, 0, 0}, o1[4] = {0, 0, 0, 0};
+    if (D == 4) {
+        clamped_offsets(i0, P.n[0], (int)P.stride[0], o0);
+        clamped_offsets(i1, P.n[1], (int)P.stride[1], o1);
+    }
+
+    // ---- LDS block: loaded rows, then ghost columns and ghost rows ----
+#pragma unroll
+    for (int k = 0; k < kPlaneStagePT; k++) {
+        const int e = tid + k * kStageBlock;
+        if (e < nload) {
+            const int rr = (int)fdiv((uint32_t)e, P.div_last);
+            const int cc = e - rr * nc;
+            lds[(lr0 - r0 + 2 + rr) * RS + cc + 2] = sv[k];
+        }
+    }
+    __syncthreads();
+    const int nghc = (lr1 - lr0) * 4;
+    for (int e = tid; e < nghc; e += kStageBlock) {
+        const int rr = e >> 2, k = e & 3;
+        T* row = lds + (lr0 + rr - r0 + 2) * RS + 2;  // row[c] is column c
+        T v;
+        int col;
+        if (k == 0) {
+            v = T(2) * row[0] - row[1];
+            col = -1;
+        } else if (k == 1) {
+            v = T(3) * row[0] - T(2) * row[1];
+            col = -2;
+        } else if (k == 2) {
+            v = T(2) * row[nc - 1] - row[nc - 2];
+            col = nc;
+        } else {
+            v = T(3) * row[nc - 1] - T(2) * row[nc - 2];
+            col = nc + 1;
+        }
+        row[col] = v;
+    }
+    const bool glo = (r0 - 2 < 0), ghi = (r1 + 2 > nr);
+    if (glo || ghi) {
+        // ghost rows -1, -2 from rows 0, 1 and nr, nr+1 from nr-1, nr-2 (the
+        // source rows are always among the loaded ones)
+        for (int e = tid; e < 2 * nc; e += kStageBlock) {
+            const int k = e >= nc ? 1 : 0, cc = e - k * nc;
+            if (glo) {
+                const T v0 = lds[(2 - r0) * RS + cc + 2], v1 = lds[(3 - r0) * RS + cc + 2];
+                const int r = k == 0 ? -1 : -2;
+                if (r >= r0 - 2)
+                    lds[(r - r0 + 2) * RS + cc + 2] = k == 0 ? T(2) * v0 - v1 : T(3) * v0 - T(2) * v1;
+            }
+            if (ghi) {
+                const T v0 = lds[(nr + 1 - r0) * RS + cc + 2], v1 = lds[(nr - r0) * RS + cc + 2];
+                const int r = k == 0 ? nr : nr + 1;
+                if (r <= r1 + 1)
+                    lds[(r - r0 + 2) * RS + cc + 2] = k == 0 ? T(2) * v0 - v1 : T(3) * v0 - T(2) * v1;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- stencil ----
+    Ham ham;
+    ham.init(P);
+    const T* ah = Prec<T>::ah(S);
+    const T dt = Prec<T>::dt(S);
+    const int order = P.order;
+    const bool edge0 = D == 4 && (i0 < 2 || i0 > P.n[0] - 3);
+    const bool edge1 = D == 4 && (i1 < 2 || i1 > P.n[1] - 3);
+    uint64_t rmax = 0;
+    // nodes two at a time: the global loads of a pair are issued together
+#pragma unroll 2
+    for (int k = 0; k < kPlaneNodesPT; k++) {
+        const int e = tid + k * kStageBlock;
+        if (e < cnt) {
+            const uint32_t gi = node0 + (uint32_t)e;
+            T w[8];
+            if (D == 4) {
+#pragma unroll
+                for (int qq = 0; qq < 4; qq++) {
+                    w[qq] = ld32(in + o0[qq], gi);
+                    w[4 + qq] = ld32(in + o1[qq], gi);
+                }
+            }
+            T vo = T(0), lvv = T(0);
+            if (STAGE == 2) {
+                vo = ld32((const T*)P.V, gi);
+                lvv = ld32((const T*)P.l, gi);
+            }
+            const int rr = (int)fdiv((uint32_t)e, P.div_last);
+            const int cc = e - rr * nc;
+            const T* q = lds + (rr + 2) * RS + cc + 2;
+            const T c = q[0];
+            T sum[4], dif;
+            eno_sum_dif<T>(q[-2 * RS], q[-RS], c, q[RS], q[2 * RS], order, sum[ra], dif);
+            T L = ah[ra] * dif;
+            eno_sum_dif<T>(q[-2], q[-1], c, q[1], q[2], order, sum[ca], dif);
+            L += ah[ca] * dif;
+            if (D == 4) {
+                T m2 = w[0], m1 = w[1], p1 = w[2], p2 = w[3];
+                if (edge0) ghost_fix<T>(i0, P.n[0], c, m2, m1, p1, p2);
+                eno_sum_dif<T>(m2, m1, c, p1, p2, order, sum[0], dif);
+                L += ah[0] * dif;
+                m2 = w[4];
+                m1 = w[5];
+                p1 = w[6];
+                p2 = w[7];
+                if (edge1) ghost_fix<T>(i1, P.n[1], c, m2, m1, p1, p2);
+                eno_sum_dif<T>(m2, m1, c, p1, p2, order, sum[1], dif);
+                L += ah[1] * dif;
+                L += ham(sum, i0, i1, r0 + rr, cc);
+            } else {
+                L += ham(sum, r0 + rr, cc, 0, 0);
+            }
+            if (STAGE == 1) {
+                st32((T*)P.Vhat, gi, c + dt * L);
+            } else {
+                const T vt = c + dt * L;
+                const T avg = T(0.5) * (vo + vt);
+                const T vn = (lvv < avg) ? lvv : avg;
+                st32((T*)P.V, gi, vn);
+                rmax = umax64(rmax, dbits(fabs((double)vn - (double)vo)));
+            }
+        }
+    }
+    __syncthreads();  // the LDS block is reused by the next tile
+    return rmax;
+}
+
+template <typename T, int STAGE>
+__device__ __forceinline__ uint64_t run_tile(const ProbDesc& P, const ProbState& S, int64_t tile,
+                                             T* lds)
+{
+    switch (P.kind) {
+    case HJR_QUAD_Z2D:
+        if (P.path == kPathPlaneS) return tile_plane<T, 2, HamZ2D<T>, STAGE, kRowStrideS>(P, S, tile, lds);
+        if (P.path == kPathPlaneL) return tile_plane<T, 2, HamZ2D<T>, STAGE, kRowStrideL>(P, S, tile, lds);
+        return tile_flat<T, 2, HamZ2D<T>, STAGE>(P, S, tile);
+    case HJR_QUAD_X4D:
+        if (P.path == kPathPlaneS) return tile_plane<T, 4, HamX4D<T>, STAGE, kRowStrideS>(P, S, tile, lds);
+        if (P.path == kPathPlaneL) return tile_plane<T, 4, HamX4D<T>, STAGE, kRowStrideL>(P, S, tile, lds);
+        return tile_flat<T, 4, HamX4D<T>, STAGE>(P, S, tile);
+    case HJR_DI2X2:
+        return tile_flat<T, 4, HamDI2X2<T>, STAGE>(P, S, tile);
+    default:
+        return 0;
+    }
+}
+
+}  // namespace hjr

@@ -1,0 +1,489 @@
+"""Thin ctypes binding of libhjr (include/hjr.h).
+
+Argument marshalling only: every step of a solve runs in the HIP kernels of
+``libhjr.so``.  PyTorch supplies device memory and the current stream.  The
+library must be built in-tree (``__graft_entry__.build()``); importing this
+module on a machine without it raises immediately -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhjr.so")
+
+OK, EINVAL, ENOMEM, NOT_CONVERGED, EDEVICE, EBUSY, ENOTFOUND = range(7)
+F32, F64 = 0, 1
+QUAD_Z2D, QUAD_X4D, DI2X2 = 0, 1, 2
+FLAG_NO_GRAPH, FLAG_NO_PIPELINE, FLAG_PROFILE, FLAG_FLAT_TILES = 1, 2, 4, 8
+
+EXPORTS = (
+    "hjr_opts_default", "hjr_strerror", "hjr_workspace_bytes", "hjr_solve", "hjr_solve_ex",
+    "hjr_interp", "hjr_refine_mask", "hjr_solve_levels", "hjr_batch_workspace_bytes",
+    "hjr_solve_batch", "hjr_server_create", "hjr_server_submit", "hjr_server_poll",
+    "hjr_server_wait", "hjr_server_read_value", "hjr_server_memory", "hjr_server_destroy",
+)
+
+
+class HjrError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+
+
+class Grid(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 4), ("lo", C.c_double * 4),
+                ("hi", C.c_double * 4)]
+
+
+class Dyn(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("p", C.c_double * 16)]
+
+
+class Dstb(C.Structure):
+    _fields_ = [("lo", C.c_double), ("hi", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("order", C.c_int32), ("cfl", C.c_double),
+                ("max_iter", C.c_int64), ("stream", C.c_void_p), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t), ("chunk", C.c_int32), ("flags", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("residual", C.c_double), ("dt", C.c_double),
+                ("alpha", C.c_double * 4), ("status", C.c_int32), ("levels", C.c_int32),
+                ("level_iterations", C.c_int64 * 4), ("cell_updates", C.c_int64),
+                ("device_ms", C.c_double), ("kernel_ms", C.c_double * 2),
+                ("kernel_launches", C.c_int64 * 2)]
+
+    def as_dict(self) -> dict:
+        return dict(iterations=self.iterations, residual=self.residual, dt=self.dt,
+                    alpha=list(self.alpha), status=self.status, levels=self.levels,
+                    level_iterations=list(self.level_iterations),
+                    cell_updates=self.cell_updates, device_ms=self.device_ms,
+                    kernel_ms=list(self.kernel_ms), kernel_launches=list(self.kernel_launches))
+
+
+class Problem(C.Structure):
+    _fields_ = [("dyn", Dyn), ("nlev", C.c_int32), ("reserved", C.c_int32),
+                ("grids", Grid * 4), ("l", C.c_void_p * 4), ("V", C.c_void_p * 4),
+                ("V0", C.c_void_p), ("d", Dstb * 2), ("tol", C.c_double)]
+
+
+class ServerCfg(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_active", C.c_int32),
+                ("dtype", C.c_int32), ("order", C.c_int32), ("chunk", C.c_int32),
+                ("cfl", C.c_double), ("max_iter", C.c_int64), ("device", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("instance_id", C.c_uint64), ("dyn", Dyn), ("grid", Grid), ("l", C.c_void_p),
+                ("d", Dstb * 2), ("tol", C.c_double), ("cold", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class Reply(C.Structure):
+    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("iterations", C.c_int64),
+                ("residual", C.c_double), ("latency_ms", C.c_double), ("queue_ms", C.c_double),
+                ("warm", C.c_int32), ("reserved2", C.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libhjr.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first "
+                          "(there is no non-HIP fallback)")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    st = C.c_int
+    L.hjr_opts_default.restype = st
+    L.hjr_opts_default.argtypes = [P(Opts)]
+    L.hjr_strerror.restype = C.c_char_p
+    L.hjr_strerror.argtypes = [st]
+    L.hjr_workspace_bytes.restype = st
+    L.hjr_workspace_bytes.argtypes = [P(Grid), P(Opts), P(C.c_size_t)]
+    L.hjr_solve.restype = st
+    L.hjr_solve.argtypes = [P(Dyn), P(Grid), C.c_void_p, C.c_void_p, P(Dstb), C.c_double,
+                            P(Opts), C.c_void_p, P(C.c_int64), P(C.c_double)]
+    L.hjr_solve_ex.restype = st
+    L.hjr_solve_ex.argtypes = [P(Dyn), P(Grid), C.c_void_p, C.c_void_p, P(Dstb), C.c_double,
+                               P(Opts), C.c_void_p, P(Stats)]
+    L.hjr_interp.restype = st
+    L.hjr_interp.argtypes = [P(Grid), C.c_void_p, P(Grid), C.c_void_p, C.c_void_p, P(Opts)]
+    L.hjr_refine_mask.restype = st
+    L.hjr_refine_mask.argtypes = [P(Grid), C.c_void_p, C.c_void_p, P(C.c_int64), P(Opts)]
+    L.hjr_solve_levels.restype = st
+    L.hjr_solve_levels.argtypes = [P(Dyn), C.c_int32, P(Grid), P(C.c_void_p), C.c_void_p,
+                                   P(Dstb), C.c_double, P(Opts), P(C.c_void_p), P(C.c_void_p),
+                                   P(C.c_int64), P(Stats)]
+    L.hjr_batch_workspace_bytes.restype = st
+    L.hjr_batch_workspace_bytes.argtypes = [C.c_int32, P(Problem), P(Opts), P(C.c_size_t)]
+    L.hjr_solve_batch.restype = st
+    L.hjr_solve_batch.argtypes = [C.c_int32, P(Problem), P(Opts), P(Stats)]
+    L.hjr_server_create.restype = st
+    L.hjr_server_create.argtypes = [P(ServerCfg), P(C.c_void_p)]
+    L.hjr_server_submit.restype = st
+    L.hjr_server_submit.argtypes = [C.c_void_p, P(Request), P(C.c_uint64)]
+    L.hjr_server_poll.restype = st
+    L.hjr_server_poll.argtypes = [C.c_void_p, C.c_uint64, P(Reply)]
+    L.hjr_server_wait.restype = st
+    L.hjr_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_double, P(Reply)]
+    L.hjr_server_read_value.restype = st
+    L.hjr_server_read_value.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_size_t]
+    L.hjr_server_memory.restype = st
+    L.hjr_server_memory.argtypes = [C.c_void_p, P(C.c_size_t), P(C.c_size_t)]
+    L.hjr_server_destroy.restype = st
+    L.hjr_server_destroy.argtypes = [C.c_void_p]
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    return lib().hjr_strerror(status).decode()
+
+
+# ---------------------------------------------------------------------------
+# struct builders
+# ---------------------------------------------------------------------------
+
+def make_grid(n, lo, hi) -> Grid:
+    g = Grid()
+    g.ndim = len(n)
+    for i in range(len(n)):
+        g.n[i] = int(n[i])
+        g.lo[i] = float(lo[i])
+        g.hi[i] = float(hi[i])
+    return g
+
+
+def make_dyn(kind: int, params) -> Dyn:
+    d = Dyn()
+    d.kind = int(kind)
+    for i, v in enumerate(params):
+        d.p[i] = float(v)
+    return d
+
+
+def make_dstb(dlo, dhi):
+    arr = (Dstb * 2)()
+    dlo = np.atleast_1d(dlo)
+    dhi = np.atleast_1d(dhi)
+    for c in range(len(dlo)):
+        arr[c].lo = float(dlo[c])
+        arr[c].hi = float(dhi[c])
+    return arr
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(dtype) -> int:
+    torch = _torch()
+    if dtype == torch.float32:
+        return F32
+    if dtype == torch.float64:
+        return F64
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+def make_opts(dtype=None, order=2, cfl=0.8, max_iter=100000, chunk=0, flags=0, stream=None) -> Opts:
+    torch = _torch()
+    o = Opts()
+    lib().hjr_opts_default(C.byref(o))
+    o.dtype = _dtype_code(dtype if dtype is not None else torch.float32)
+    o.order = order
+    o.cfl = cfl
+    o.max_iter = max_iter
+    o.chunk = chunk
+    o.flags = flags
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    o.stream = C.c_void_p(stream.cuda_stream)
+    return o
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_tensor(t, n, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: need contiguous {dtype} with {n} elements, got "
+                         f"{t.dtype} {tuple(t.shape)}")
+
+
+def _raise(status, what, allow=(OK,)):
+    if status not in allow:
+        raise HjrError(status, what)
+
+
+# ---------------------------------------------------------------------------
+# solves
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Spec:
+    """Model + grid + bounds of one subsystem, in plain Python values."""
+    kind: int
+    params: tuple
+    n: tuple
+    lo: tuple
+    hi: tuple
+    dlo: tuple
+    dhi: tuple
+    tol: float = 1e-4
+
+    @classmethod
+    def of(cls, p) -> "Spec":
+        return cls(p.kind, tuple(p.params), tuple(p.n), tuple(p.lo), tuple(p.hi),
+                   tuple(p.dlo), tuple(p.dhi), p.tol)
+
+    @property
+    def size(self) -> int:
+        return int(np.prod(self.n))
+
+
+def workspace_bytes(spec: Spec, opts: Opts) -> int:
+    out = C.c_size_t(0)
+    g = make_grid(spec.n, spec.lo, spec.hi)
+    _raise(lib().hjr_workspace_bytes(C.byref(g), C.byref(opts), C.byref(out)),
+           "hjr_workspace_bytes")
+    return out.value
+
+
+def solve(spec: Spec, l, V0=None, V_out=None, *, dtype=None, order=2, cfl=0.8,
+          max_iter=100000, chunk=0, flags=0, workspace=True, check=True):
+    """One safe-set solve.  l, V0, V_out: device tensors of spec.size elements.
+    Returns (V_out, stats dict).  Raises HjrError on failure; a solve that
+    hits max_iter returns with stats['status'] == NOT_CONVERGED."""
+    torch = _torch()
+    dtype = dtype or l.dtype
+    N = spec.size
+    _check_tensor(l, N, dtype, "l")
+    if V0 is not None:
+        _check_tensor(V0, N, dtype, "V0")
+    if V_out is None:
+        V_out = torch.empty(N, dtype=dtype, device=l.device)
+    _check_tensor(V_out, N, dtype, "V_out")
+    o = make_opts(dtype, order, cfl, max_iter, chunk, flags)
+    ws = None
+    if workspace:
+        nb = workspace_bytes(spec, o)
+        ws = torch.empty(nb, dtype=torch.uint8, device=l.device)
+        o.workspace = C.c_void_p(ws.data_ptr())
+        o.workspace_bytes = nb
+    st = Stats()
+    g = make_grid(spec.n, spec.lo, spec.hi)
+    dyn = make_dyn(spec.kind, spec.params)
+    d = make_dstb(spec.dlo, spec.dhi)
+    r = lib().hjr_solve_ex(C.byref(dyn), C.byref(g), _ptr(l), _ptr(V0), d, spec.tol,
+                           C.byref(o), _ptr(V_out), C.byref(st))
+    if check:
+        _raise(r, "hjr_solve_ex", (OK, NOT_CONVERGED))
+    del ws
+    out = st.as_dict()
+    out["return"] = r
+    return V_out, out
+
+
+def solve_levels(spec: Spec, grids_n, ls, V0=None, *, dtype=None, order=2, cfl=0.8,
+                 max_iter=100000, chunk=0, flags=0, masks=False):
+    """Coarse-to-fine solve: grids_n is a list of per-level node counts over
+    spec's box, ls the per-level constraints.  Returns (list of V per level,
+    list of masks or None, mask counts, stats)."""
+    torch = _torch()
+    nlev = len(grids_n)
+    dtype = dtype or ls[0].dtype
+    grids = (Grid * nlev)(*[make_grid(n, spec.lo, spec.hi) for n in grids_n])
+    Vs = [torch.empty(int(np.prod(n)), dtype=dtype, device=ls[0].device) for n in grids_n]
+    for k in range(nlev):
+        _check_tensor(ls[k], int(np.prod(grids_n[k])), dtype, f"l[{k}]")
+    lp = (C.c_void_p * nlev)(*[t.data_ptr() for t in ls])
+    vp = (C.c_void_p * nlev)(*[t.data_ptr() for t in Vs])
+    mk = None
+    mp = None
+    counts = (C.c_int64 * nlev)()
+    if masks:
+        mk = [torch.zeros(int(np.prod([x - 1 for x in n])), dtype=torch.uint8,
+                          device=ls[0].device) for n in grids_n]
+        mp = (C.c_void_p * nlev)(*[t.data_ptr() for t in mk])
+    o = make_opts(dtype, order, cfl, max_iter, chunk, flags)
+    st = Stats()
+    dyn = make_dyn(spec.kind, spec.params)
+    d = make_dstb(spec.dlo, spec.dhi)
+    r = lib().hjr_solve_levels(C.byref(dyn), nlev, grids, lp, _ptr(V0), d, spec.tol,
+                               C.byref(o), vp, mp, counts if masks else None, C.byref(st))
+    _raise(r, "hjr_solve_levels", (OK, NOT_CONVERGED))
+    out = st.as_dict()
+    out["return"] = r
+    return Vs, mk, (list(counts) if masks else None), out
+
+
+def make_problem(spec: Spec, l, V_out, V0=None, levels=None) -> Problem:
+    """levels: optional list of (n, l_k, V_k) for a coarse-to-fine job; else
+    one level with (spec.n, l, V_out)."""
+    p = Problem()
+    p.dyn = make_dyn(spec.kind, spec.params)
+    if levels is None:
+        levels = [(spec.n, l, V_out)]
+    p.nlev = len(levels)
+    for k, (n, lk, Vk) in enumerate(levels):
+        p.grids[k] = make_grid(n, spec.lo, spec.hi)
+        p.l[k] = lk.data_ptr()
+        p.V[k] = Vk.data_ptr()
+    p.V0 = V0.data_ptr() if V0 is not None else None
+    dd = make_dstb(spec.dlo, spec.dhi)
+    p.d[0] = dd[0]
+    p.d[1] = dd[1]
+    p.tol = spec.tol
+    return p
+
+
+def solve_batch(problems, *, dtype=None, order=2, cfl=0.8, max_iter=100000, chunk=0,
+                flags=0, device=None):
+    """problems: list of Problem structs (make_problem).  Returns (return
+    status, list of stats dicts)."""
+    torch = _torch()
+    n = len(problems)
+    arr = (Problem * n)(*problems)
+    o = make_opts(dtype or torch.float32, order, cfl, max_iter, chunk, flags)
+    nb = C.c_size_t(0)
+    _raise(lib().hjr_batch_workspace_bytes(n, arr, C.byref(o), C.byref(nb)),
+           "hjr_batch_workspace_bytes")
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=device or "cuda")
+    o.workspace = C.c_void_p(ws.data_ptr())
+    o.workspace_bytes = nb.value
+    res = (Stats * n)()
+    r = lib().hjr_solve_batch(n, arr, C.byref(o), res)
+    _raise(r, "hjr_solve_batch", (OK, NOT_CONVERGED))
+    del ws
+    return r, [res[i].as_dict() for i in range(n)]
+
+
+def interp(src_n, Vs, dst_n, lo, hi, l_dst=None, out=None):
+    torch = _torch()
+    src = make_grid(src_n, lo, hi)
+    dst = make_grid(dst_n, lo, hi)
+    Nd = int(np.prod(dst_n))
+    if out is None:
+        out = torch.empty(Nd, dtype=Vs.dtype, device=Vs.device)
+    o = make_opts(Vs.dtype)
+    _raise(lib().hjr_interp(C.byref(src), _ptr(Vs), C.byref(dst), _ptr(out), _ptr(l_dst),
+                            C.byref(o)), "hjr_interp")
+    return out
+
+
+def refine_mask(n, lo, hi, V):
+    torch = _torch()
+    g = make_grid(n, lo, hi)
+    m = torch.empty(int(np.prod([x - 1 for x in n])), dtype=torch.uint8, device=V.device)
+    cnt = C.c_int64(0)
+    o = make_opts(V.dtype)
+    _raise(lib().hjr_refine_mask(C.byref(g), _ptr(V), _ptr(m), C.byref(cnt), C.byref(o)),
+           "hjr_refine_mask")
+    return m, cnt.value
+
+
+# ---------------------------------------------------------------------------
+# server
+# ---------------------------------------------------------------------------
+
+class Server:
+    """Continuous-batching safe-set update server (hjr_server_*)."""
+
+    def __init__(self, hbm_budget_bytes=0, max_active=256, dtype=F32, order=2, chunk=0,
+                 cfl=0.8, max_iter=100000, device=0, flags=0):
+        c = ServerCfg()
+        c.hbm_budget_bytes = hbm_budget_bytes
+        c.max_active = max_active
+        c.dtype = dtype
+        c.order = order
+        c.chunk = chunk
+        c.cfl = cfl
+        c.max_iter = max_iter
+        c.device = device
+        c.flags = flags
+        self.dtype = dtype
+        h = C.c_void_p()
+        _raise(lib().hjr_server_create(C.byref(c), C.byref(h)), "hjr_server_create")
+        self._h = h
+
+    def submit(self, instance_id: int, spec: Spec, l_host=None, cold=False) -> int:
+        req = Request()
+        req.instance_id = instance_id
+        req.dyn = make_dyn(spec.kind, spec.params)
+        req.grid = make_grid(spec.n, spec.lo, spec.hi)
+        keep = None
+        if l_host is not None:
+            keep = np.ascontiguousarray(l_host, dtype=np.float64 if self.dtype == F64 else np.float32)
+            req.l = keep.ctypes.data
+        dd = make_dstb(spec.dlo, spec.dhi)
+        req.d[0] = dd[0]
+        req.d[1] = dd[1]
+        req.tol = spec.tol
+        req.cold = 1 if cold else 0
+        t = C.c_uint64(0)
+        _raise(lib().hjr_server_submit(self._h, C.byref(req), C.byref(t)), "hjr_server_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        rep = Reply()
+        r = lib().hjr_server_poll(self._h, ticket, C.byref(rep))
+        if r == EBUSY:
+            return None
+        _raise(r, "hjr_server_poll")
+        return _reply_dict(rep)
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0):
+        rep = Reply()
+        r = lib().hjr_server_wait(self._h, ticket, timeout_ms, C.byref(rep))
+        if r == EBUSY:
+            return None
+        _raise(r, "hjr_server_wait")
+        return _reply_dict(rep)
+
+    def read_value(self, instance_id: int, size: int):
+        out = np.empty(size, dtype=np.float64 if self.dtype == F64 else np.float32)
+        _raise(lib().hjr_server_read_value(self._h, instance_id, out.ctypes.data, out.nbytes),
+               "hjr_server_read_value")
+        return out
+
+    def memory(self):
+        u = C.c_size_t(0)
+        b = C.c_size_t(0)
+        _raise(lib().hjr_server_memory(self._h, C.byref(u), C.byref(b)), "hjr_server_memory")
+        return u.value, b.value
+
+    def close(self):
+        if self._h:
+            r = lib().hjr_server_destroy(self._h)
+            self._h = None
+            _raise(r, "hjr_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def _reply_dict(rep: Reply) -> dict:
+    return dict(status=rep.status, iterations=rep.iterations, residual=rep.residual,
+                latency_ms=rep.latency_ms, queue_ms=rep.queue_ms, warm=bool(rep.warm))

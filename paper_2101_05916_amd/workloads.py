@@ -1,0 +1,163 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+This module holds problem *inputs* only -- grid boxes, model parameters,
+constraint functions l(x) and seeded request mixes.  It holds none of the
+solver's arithmetic, and it imports neither the device library nor the
+oracle, so both sides can be fed the same arrays.
+
+Models (paper Sec. IV eq. (3) and Sec. V), in the sign convention where
+l > 0 inside the constraint set:
+
+* vertical quadcopter / z-subsystem, state (z, vz):
+  z' = vz, vz' = 0.91 u - 9.81 + d, u in [7, 16];
+  box z in [0, 3], vz in [-4, 4]; l = min(z - 0.5, 2.5 - z).
+* x-subsystem of the near-hover quadcopter, state (x, vx, theta, omega):
+  x' = vx + d, vx' = 9.81 tan(theta), theta' = -8 theta + omega,
+  omega' = -10 theta + 10 S, |S| <= pi/9;
+  box x in [-5, 5], vx in [-2, 2], theta in [-pi/6, pi/6], omega in [-2, 2];
+  l = 4 - |x|.
+* DI2X2 (test-only): two independent vertical models on one 4-D grid, in any
+  assignment of their four coordinates to the grid axes.
+
+The paper's own workloads come from a simulator and GP-learned bounds that
+are not available; scalar symmetric disturbance bounds [-dbar, dbar] stand in.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+QUAD_Z2D, QUAD_X4D, DI2X2 = 0, 1, 2
+
+Z2D_PARAMS = (0.91, 9.81, 7.0, 16.0)           # k, g, u_lo, u_hi
+X4D_PARAMS = (9.81, 8.0, 10.0, 10.0, math.pi / 9)  # g, d1, d0, n0, s_max
+Z2D_BOX = ((0.0, -4.0), (3.0, 4.0))
+X4D_BOX = ((-5.0, -2.0, -math.pi / 6, -2.0), (5.0, 2.0, math.pi / 6, 2.0))
+
+
+@dataclass
+class Problem:
+    """One subsystem solve: model, grid, constraint array, bounds."""
+    kind: int
+    params: tuple
+    n: tuple
+    lo: tuple
+    hi: tuple
+    l: np.ndarray               # float64, flattened row-major
+    dlo: tuple
+    dhi: tuple
+    tol: float = 1e-4
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ndim(self) -> int:
+        return len(self.n)
+
+    @property
+    def size(self) -> int:
+        return int(np.prod(self.n))
+
+
+def axes(n, lo, hi):
+    """Node coordinates per axis: lo + j (hi - lo)/(n - 1), both ends included."""
+    return [lo[i] + np.arange(n[i], dtype=np.float64) * ((hi[i] - lo[i]) / (n[i] - 1))
+            for i in range(len(n))]
+
+
+def mesh(n, lo, hi):
+    return np.meshgrid(*axes(n, lo, hi), indexing="ij")
+
+
+def l_z2d(n, lo=Z2D_BOX[0], hi=Z2D_BOX[1], zmin=0.5, zmax=2.5):
+    """Signed distance to zmin <= z <= zmax (positive inside)."""
+    Z, _ = mesh(n, lo, hi)
+    return np.minimum(Z - zmin, zmax - Z).ravel()
+
+
+def l_x4d(n, lo=X4D_BOX[0], hi=X4D_BOX[1], xmax=4.0):
+    """Signed distance to |x| <= xmax (positive inside)."""
+    X = mesh(n, lo, hi)[0]
+    return (xmax - np.abs(X)).ravel()
+
+
+def quad_z2d(n=101, dbar=0.5, name="z2d") -> Problem:
+    nn = (n, n) if np.isscalar(n) else tuple(n)
+    return Problem(QUAD_Z2D, Z2D_PARAMS, nn, Z2D_BOX[0], Z2D_BOX[1], l_z2d(nn),
+                   (-dbar,), (dbar,), name=name)
+
+
+def quad_x4d(n=41, dbar=0.5, name="x4d") -> Problem:
+    nn = (n,) * 4 if np.isscalar(n) else tuple(n)
+    return Problem(QUAD_X4D, X4D_PARAMS, nn, X4D_BOX[0], X4D_BOX[1], l_x4d(nn),
+                   (-dbar,), (dbar,), name=name)
+
+
+def di2x2(n=21, perm=(0, 1, 2, 3), dbar=(0.5, 0.3), name="di2x2") -> Problem:
+    """Two vertical models: copy a on axes (perm[0], perm[1]) = (z_a, v_a), copy b
+    on (perm[2], perm[3]).  Each axis gets the box of the coordinate it holds."""
+    nn = (n,) * 4 if np.isscalar(n) else tuple(n)
+    lo = [0.0] * 4
+    hi = [0.0] * 4
+    for role, ax in enumerate(perm):
+        z_or_v = role % 2
+        lo[ax] = Z2D_BOX[0][z_or_v]
+        hi[ax] = Z2D_BOX[1][z_or_v]
+    G = mesh(nn, lo, hi)
+    za, zb = G[perm[0]], G[perm[2]]
+    l = np.minimum(np.minimum(za - 0.5, 2.5 - za), np.minimum(zb - 0.5, 2.5 - zb)).ravel()
+    params = Z2D_PARAMS + Z2D_PARAMS + tuple(float(p) for p in perm)
+    return Problem(DI2X2, params, nn, tuple(lo), tuple(hi), l,
+                   (-dbar[0], -dbar[1]), (dbar[0], dbar[1]), name=name)
+
+
+def decomposed_quad10d(n4=41, n2=101, dbar=0.5):
+    """The near-hover quadcopter of eq. (3) split into its x, y (4-D) and z
+    (2-D) subsystems (paper Sec. III-A, Sec. IV-A).  y is identical to x."""
+    return [quad_x4d(n4, dbar, "x"), quad_x4d(n4, dbar, "y"), quad_z2d(n2, dbar, "z")]
+
+
+def batch_manifest(count=256, seed=0):
+    """Seeded mix of independent subsystem solves: type 2-D or 4-D with
+    probability 1/2, 2-D sizes uniform in 51..201, 4-D sizes uniform in
+    31..61 (all axes equal), bounds dbar uniform in [0.2, 1.0]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        is4 = bool(rng.random() < 0.5)
+        n = int(rng.integers(31, 62)) if is4 else int(rng.integers(51, 202))
+        dbar = float(rng.uniform(0.2, 1.0))
+        out.append(dict(index=i, kind=QUAD_X4D if is4 else QUAD_Z2D, n=n, dbar=dbar))
+    return out
+
+
+def problem_from_manifest(entry) -> Problem:
+    if entry["kind"] == QUAD_X4D:
+        return quad_x4d(entry["n"], entry["dbar"], name=f"b{entry['index']}")
+    return quad_z2d(entry["n"], entry["dbar"], name=f"b{entry['index']}")
+
+
+SERVE_CLASSES = (("2d", 51), ("2d", 101), ("2d", 201), ("4d", 31), ("4d", 41), ("4d", 61))
+
+
+def serve_stream(count=3000, rate=200.0, instances_per_class=4, seed=1,
+                 classes=SERVE_CLASSES):
+    """Poisson arrivals (exponential gaps of mean 1/rate seconds) of safe-set
+    update requests.  Each picks one of the instances uniformly and a new
+    dbar uniform in [0.2, 1.0]."""
+    rng = np.random.default_rng(seed)
+    insts = []
+    for cls, n in classes:
+        for k in range(instances_per_class):
+            insts.append(dict(instance=len(insts), kind=QUAD_X4D if cls == "4d" else QUAD_Z2D,
+                              n=n))
+    t = 0.0
+    reqs = []
+    for i in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        inst = insts[int(rng.integers(0, len(insts)))]
+        reqs.append(dict(seq=i, t=t, instance=inst["instance"], kind=inst["kind"],
+                         n=inst["n"], dbar=float(rng.uniform(0.2, 1.0))))
+    return insts, reqs

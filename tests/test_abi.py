@@ -1,0 +1,167 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports
+every entry point that include/hjr.h declares, the ctypes structs have the
+C layouts, and argument validation rejects bad input before touching the
+device."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2101_05916_amd import hjr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hjr.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hjr_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = hjr.lib()
+    names = declared_functions()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(hjr.EXPORTS)
+
+
+def test_struct_layouts_match_c():
+    prog = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "hjr.h"
+int main(void){
+ printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hjr_grid), sizeof(hjr_dyn),
+   sizeof(hjr_dstb), sizeof(hjr_opts), sizeof(hjr_stats), sizeof(hjr_problem),
+   sizeof(hjr_server_cfg), sizeof(hjr_request), sizeof(hjr_reply));
+ printf("%zu %zu %zu %zu\n", offsetof(hjr_opts, flags), offsetof(hjr_stats, kernel_launches),
+   offsetof(hjr_problem, tol), offsetof(hjr_request, cold));
+ return 0; }
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(prog)
+        subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.check_output([exe]).decode().split()
+    got = [int(x) for x in out]
+    want = [C.sizeof(hjr.Grid), C.sizeof(hjr.Dyn), C.sizeof(hjr.Dstb), C.sizeof(hjr.Opts),
+            C.sizeof(hjr.Stats), C.sizeof(hjr.Problem), C.sizeof(hjr.ServerCfg),
+            C.sizeof(hjr.Request), C.sizeof(hjr.Reply),
+            hjr.Opts.flags.offset, hjr.Stats.kernel_launches.offset, hjr.Problem.tol.offset,
+            hjr.Request.cold.offset]
+    assert got == want
+
+
+def test_defaults_and_strerror():
+    L = hjr.lib()
+    o = hjr.Opts()
+    assert L.hjr_opts_default(C.byref(o)) == hjr.OK
+    assert (o.dtype, o.order, o.cfl, o.max_iter) == (hjr.F32, 2, 0.8, 100000)
+    assert L.hjr_opts_default(None) == hjr.EINVAL
+    for s in range(7):
+        assert L.hjr_strerror(s)
+    assert L.hjr_strerror(99) == b"unknown status"
+
+
+def _opts(**kw):
+    o = hjr.Opts()
+    hjr.lib().hjr_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def test_workspace_bytes():
+    L = hjr.lib()
+    g = hjr.make_grid((41, 41, 41, 41), (-5, -2, -0.5, -2), (5, 2, 0.5, 2))
+    out = C.c_size_t(0)
+    assert L.hjr_workspace_bytes(C.byref(g), C.byref(_opts()), C.byref(out)) == hjr.OK
+    assert out.value >= 41 ** 4 * 4
+    out64 = C.c_size_t(0)
+    assert L.hjr_workspace_bytes(C.byref(g), C.byref(_opts(dtype=hjr.F64)), C.byref(out64)) == hjr.OK
+    assert out64.value > out.value
+    bad = hjr.make_grid((2, 41), (0, 0), (1, 1))
+    assert L.hjr_workspace_bytes(C.byref(bad), None, C.byref(out)) == hjr.EINVAL
+
+
+@pytest.mark.parametrize("what", ["n<3", "lo>=hi", "ndim", "tol", "cfl", "order", "dstb",
+                                  "kind", "null_l", "theta_range", "max_iter", "perm"])
+def test_solve_rejects_invalid_arguments_without_device(what):
+    """Every one of these returns EINVAL before any HIP call (no GPU here)."""
+    L = hjr.lib()
+    n, lo, hi = [51, 51], [0.0, -4.0], [3.0, 4.0]
+    kind, params = hjr.QUAD_Z2D, (0.91, 9.81, 7.0, 16.0)
+    tol, kw = 1e-4, {}
+    dlo, dhi = [-0.5], [0.5]
+    lptr = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    if what == "n<3":
+        n = [2, 51]
+    elif what == "lo>=hi":
+        hi = [0.0, 4.0]
+    elif what == "ndim":
+        n, lo, hi = [51] * 4, [0.0] * 4, [1.0] * 4
+    elif what == "tol":
+        tol = 0.0
+    elif what == "cfl":
+        kw = dict(cfl=1.5)
+    elif what == "order":
+        kw = dict(order=3)
+    elif what == "dstb":
+        dlo, dhi = [0.5], [-0.5]
+    elif what == "kind":
+        kind = 7
+    elif what == "null_l":
+        lptr = None
+    elif what == "theta_range":
+        kind, params = hjr.QUAD_X4D, (9.81, 8, 10, 10, 0.349)
+        n, lo, hi = [11] * 4, [-5, -2, -2.0, -2], [5, 2, 2.0, 2]
+    elif what == "max_iter":
+        kw = dict(max_iter=0)
+    elif what == "perm":
+        kind = hjr.DI2X2
+        params = (0.91, 9.81, 7, 16, 0.91, 9.81, 7, 16, 0, 1, 1, 3)
+        n, lo, hi = [11] * 4, [0.0] * 4, [1.0] * 4
+        dlo, dhi = [-0.5, -0.5], [0.5, 0.5]
+    g = hjr.make_grid(n, lo, hi)
+    dyn = hjr.make_dyn(kind, params)
+    d = hjr.make_dstb(dlo, dhi)
+    it = C.c_int64(0)
+    res = C.c_double(0)
+    r = L.hjr_solve(C.byref(dyn), C.byref(g), lptr, None, d, tol, C.byref(_opts(**kw)),
+                    C.c_void_p(0x2000), C.byref(it), C.byref(res))
+    assert r == hjr.EINVAL
+
+
+def test_interp_and_mask_reject_invalid():
+    L = hjr.lib()
+    a = hjr.make_grid((11, 11), (0, 0), (1, 1))
+    b = hjr.make_grid((21, 21), (0, 0), (1, 2))  # different box
+    p = C.c_void_p(0x1000)
+    q = C.c_void_p(0x2000)
+    assert L.hjr_interp(C.byref(a), p, C.byref(b), q, None, None) == hjr.EINVAL
+    assert L.hjr_interp(C.byref(a), p, C.byref(a), p, None, None) == hjr.EINVAL  # aliasing
+    bad = hjr.make_grid((1, 11), (0, 0), (1, 1))
+    assert L.hjr_refine_mask(C.byref(bad), p, q, None, None) == hjr.EINVAL
+
+
+def test_batch_and_server_reject_invalid():
+    L = hjr.lib()
+    out = C.c_size_t(0)
+    assert L.hjr_batch_workspace_bytes(0, None, None, C.byref(out)) == hjr.EINVAL
+    assert L.hjr_solve_batch(0, None, None, None) == hjr.EINVAL
+    h = C.c_void_p()
+    cfg = hjr.ServerCfg()
+    cfg.dtype = 5
+    assert L.hjr_server_create(C.byref(cfg), C.byref(h)) == hjr.EINVAL
+    assert L.hjr_server_submit(None, None, None) == hjr.EINVAL
+    assert L.hjr_server_poll(None, 1, None) == hjr.EINVAL
+    assert L.hjr_server_destroy(None) == hjr.EINVAL
