@@ -85,6 +85,7 @@ struct hjr_server {
     std::map<uint64_t, Instance> inst;
     std::map<uint64_t, int> pending;                     // queued + running tickets per instance
     std::map<uint64_t, std::vector<char>> l_host;        // host copy of each instance's constraint
+    std::map<uint64_t, std::pair<hjr_grid, int32_t>> shape;  // grid and model of every instance seen
     std::map<size_t, std::vector<void*>> cache;  // free blocks by size
     uint64_t next_ticket = 1;
     uint64_t use_clock = 0;
@@ -400,15 +401,17 @@ hjr_status hjr_server_submit(hjr_server* s, const hjr_request* req, uint64_t* ti
     const size_t bytes = grid_size(g) * s->esz();
     std::lock_guard<std::mutex> lk(s->m);
     if (s->fatal != HJR_OK) return s->fatal;
-    auto ii = s->inst.find(req->instance_id);
-    if (ii != s->inst.end()) {
-        const hjr_grid& h = ii->second.grid;
-        if (std::memcmp(&h, &g, sizeof(g)) != 0 || ii->second.dyn.kind != req->dyn.kind)
-            return HJR_EINVAL;
+    // an instance keeps its grid and model; its first request brings l
+    auto sh = s->shape.find(req->instance_id);
+    if (sh != s->shape.end()) {
+        const hjr_grid& h = sh->second.first;
+        bool same = h.ndim == g.ndim && sh->second.second == req->dyn.kind;
+        for (int i = 0; same && i < g.ndim; i++)
+            same = h.n[i] == g.n[i] && h.lo[i] == g.lo[i] && h.hi[i] == g.hi[i];
+        if (!same) return HJR_EINVAL;
+    } else if (!req->l) {
+        return HJR_EINVAL;
     }
-    // the first request of an instance must bring its constraint
-    const bool seen = s->l_host.count(req->instance_id) > 0 || s->pending[req->instance_id] > 0;
-    if (!req->l && !seen) return HJR_EINVAL;
     const size_t table = Engine::table_bytes(s->cfg.max_active, s->cfg.chunk);
     if (align256(table) + s->instance_bytes(g) + s->work_bytes(g) > s->budget) return HJR_ENOMEM;
     if (req->l) {
@@ -419,6 +422,7 @@ hjr_status hjr_server_submit(hjr_server* s, const hjr_request* req, uint64_t* ti
     t->id = s->next_ticket++;
     *ticket = t->id;
     s->pending[req->instance_id]++;
+    s->shape[req->instance_id] = {g, req->dyn.kind};
     s->queue.push_back(t->id);
     s->tickets[t->id] = std::move(t);
     s->cv_work.notify_all();
