@@ -27,6 +27,39 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f)
     return __umulhi(x, f.m) >> f.s;
 }
 
+// Global-memory access through an explicit global address space: the
+// problem table hands out generic pointers, and a generic (flat) access both
+// costs a 64-bit address add per load and counts against the LDS wait
+// counter, so every LDS wait would also wait for outstanding global loads.
+#define HJR_GLOBAL __attribute__((address_space(1)))
+
+// Element i (32-bit; the host keeps N * sizeof(T) < 2^32 where these are
+// used) of a uniform base pointer: one SGPR pair plus one VGPR offset.
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, uint32_t i)
+{
+    return *(const HJR_GLOBAL T*)((const HJR_GLOBAL char*)base + i * (uint32_t)sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ void st32(T* base, uint32_t i, T v)
+{
+    *(HJR_GLOBAL T*)((HJR_GLOBAL char*)base + i * (uint32_t)sizeof(T)) = v;
+}
+
+// Element i (any 64-bit index) of a global array.
+template <typename T>
+__device__ __forceinline__ T ld64(const T* base, int64_t i)
+{
+    return ((const HJR_GLOBAL T*)base)[i];
+}
+
+template <typename T>
+__device__ __forceinline__ void st64(T* base, int64_t i, T v)
+{
+    ((HJR_GLOBAL T*)base)[i] = v;
+}
+
 template <typename T>
 struct Prec;
 template <>
@@ -49,6 +82,16 @@ struct Prec<double> {
 };
 
 // sum and dif of one axis from its five samples (see the header comment).
+template <typename T>
+__device__ __forceinline__ void eno_sum_dif(T w0, T w1, T w2, T w3, T w4, int order, T& sum, T& dif);
+
+// ORDER fixed at compile time (2 = ENO2, 1 = first order).
+template <typename T, int ORDER>
+__device__ __forceinline__ void eno_sd(T w0, T w1, T w2, T w3, T w4, T& sum, T& dif)
+{
+    eno_sum_dif<T>(w0, w1, w2, w3, w4, ORDER, sum, dif);
+}
+
 template <typename T>
 __device__ __forceinline__ void eno_sum_dif(T w0, T w1, T w2, T w3, T w4, int order, T& sum, T& dif)
 {
@@ -81,38 +124,6 @@ __device__ __forceinline__ void ghost_fix(int j, int n, T c, T& m2, T& m1, T& p1
     m1 = m1f;
     p1 = p1f;
     p2 = p2f;
-}
-
-// Load through a uniform base pointer and a 32-bit element offset.
-template <typename T>
-__device__ __forceinline__ T ldg(const T* base, uint32_t i)
-{
-    return *(const T*)((const char*)base + (size_t)i * sizeof(T));
-}
-
-// Samples of one axis through a global array at element gi, for a position
-// j along that axis that is the same in the whole workgroup (uniform), so
-// the boundary test is a scalar branch.
-template <typename T>
-__device__ __forceinline__ void axis_global_uniform(const T* __restrict__ in, uint32_t gi, int j,
-                                                    int n, int s, T c, T& w0, T& w1, T& w3, T& w4)
-{
-    if (j >= 2 && j <= n - 3) {
-        w0 = ldg(in - 2 * s, gi);
-        w1 = ldg(in - s, gi);
-        w3 = ldg(in + s, gi);
-        w4 = ldg(in + 2 * s, gi);
-    } else {
-        const int om2 = j >= 2 ? 2 * s : (j >= 1 ? s : 0);
-        const int om1 = j >= 1 ? s : 0;
-        const int op1 = j <= n - 2 ? s : 0;
-        const int op2 = j <= n - 3 ? 2 * s : (j <= n - 2 ? s : 0);
-        w0 = ldg(in - om2, gi);
-        w1 = ldg(in - om1, gi);
-        w3 = ldg(in + op1, gi);
-        w4 = ldg(in + op2, gi);
-        ghost_fix<T>(j, n, c, w0, w1, w3, w4);
-    }
 }
 
 // ------------------------------------------------------------------------
@@ -173,7 +184,7 @@ struct HamX4D {
         const T tw = A + (T)j3 * B - (T)j2 * C;          // (0.5/h2)(omega - d1 theta)
         const T t3 = D + (T)j2 * E;                      // (0.5/h3) d0 theta
         const T s0 = sum[0];
-        return s0 * (cvx + (s0 >= T(0) ? dl : dh)) + sum[1] * gts[j2] + sum[2] * tw -
+        return s0 * (cvx + (s0 >= T(0) ? dl : dh)) + sum[1] * ld32(gts, (uint32_t)j2) + sum[2] * tw -
                sum[3] * t3 + n0s * fabs(sum[3]);
     }
 };
@@ -242,19 +253,18 @@ __device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b)
 // Stage 1 writes Vhat = c + dt L.  Stage 2 writes V' = min(l, (V + c + dt L)/2)
 // over V and folds |V' - V| (in double) into rmax.
 template <typename T, int STAGE>
-__device__ __forceinline__ void finish_node(const ProbDesc& P, uint32_t gi, T c, T L, T dt,
+__device__ __forceinline__ void finish_node(const ProbDesc& P, int64_t gi, T c, T L, T dt,
                                             uint64_t& rmax)
 {
     if (STAGE == 1) {
-        *(T*)((char*)P.Vhat + (size_t)gi * sizeof(T)) = c + dt * L;
+        st64((T*)P.Vhat, gi, c + dt * L);
     } else {
-        T* vp = (T*)((char*)P.V + (size_t)gi * sizeof(T));
         const T vt = c + dt * L;
-        const T vo = *vp;
+        const T vo = ld64((const T*)P.V, gi);
         const T avg = T(0.5) * (vo + vt);
-        const T lv = ldg((const T*)P.l, gi);
+        const T lv = ld64((const T*)P.l, gi);
         const T vn = (lv < avg) ? lv : avg;
-        *vp = vn;
+        st64((T*)P.V, gi, vn);
         rmax = umax64(rmax, dbits(fabs((double)vn - (double)vo)));
     }
 }
@@ -287,16 +297,16 @@ __device__ uint64_t tile_flat(const ProbDesc& P, const ProbState& S, int64_t til
             q = qq;
         }
         j[0] = (int)q;
-        const T c = in[idx];
+        const T c = ld64(in, idx);
         T sum[4] = {0, 0, 0, 0};
         T L = T(0);
 #pragma unroll
         for (int a = 0; a < D; a++) {
             const int s = (int)P.stride[a], n = P.n[a];
-            T m2 = in[idx - (j[a] >= 2 ? 2 * s : (j[a] >= 1 ? s : 0))];
-            T m1 = in[idx - (j[a] >= 1 ? s : 0)];
-            T p1 = in[idx + (j[a] <= n - 2 ? s : 0)];
-            T p2 = in[idx + (j[a] <= n - 3 ? 2 * s : (j[a] <= n - 2 ? s : 0))];
+            T m2 = ld64(in, idx - (j[a] >= 2 ? 2 * s : (j[a] >= 1 ? s : 0)));
+            T m1 = ld64(in, idx - (j[a] >= 1 ? s : 0));
+            T p1 = ld64(in, idx + (j[a] <= n - 2 ? s : 0));
+            T p2 = ld64(in, idx + (j[a] <= n - 3 ? 2 * s : (j[a] <= n - 2 ? s : 0)));
             ghost_fix<T>(j[a], n, c, m2, m1, p1, p2);
             T dif;
             eno_sum_dif<T>(m2, m1, c, p1, p2, order, sum[a], dif);
@@ -306,7 +316,7 @@ __device__ uint64_t tile_flat(const ProbDesc& P, const ProbState& S, int64_t til
             L += ham(sum, j[0], j[1], 0, 0);
         else
             L += ham(sum, j[0], j[1], j[2], j[3]);
-        finish_node<T, STAGE>(P, (uint32_t)idx, c, L, dt, rmax);
+        finish_node<T, STAGE>(P, (int64_t)idx, c, L, dt, rmax);
     }
     return rmax;
 }
@@ -314,21 +324,6 @@ __device__ uint64_t tile_flat(const ProbDesc& P, const ProbState& S, int64_t til
 // ------------------------------------------------------------------------
 // plane tiles: rows of the two fastest axes staged in LDS with ghosts
 // ------------------------------------------------------------------------
-
-// Load / store through a uniform base pointer and a 32-bit byte offset
-// (the host keeps N * sizeof(T) < 2^32 for plane tiles), so the address is
-// one SGPR pair plus one VGPR and costs no 64-bit vector arithmetic.
-template <typename T>
-__device__ __forceinline__ T ld32(const T* base, uint32_t i)
-{
-    return *(const T*)((const char*)base + i * (uint32_t)sizeof(T));
-}
-
-template <typename T>
-__device__ __forceinline__ void st32(T* base, uint32_t i, T v)
-{
-    *(T*)((char*)base + i * (uint32_t)sizeof(T)) = v;
-}
 
 // Clamped offsets of the samples j-2, j-1, j+1, j+2 along an axis of stride
 // s and length n (out-of-range samples read the centre; ghost_fix replaces
@@ -348,7 +343,7 @@ __device__ __forceinline__ void clamped_offsets(int j, int n, int s, int* o)
 // of the nodes are loaded two nodes at a time.  The LDS block has columns -2 .. n_last+1 (stride RS);
 // out-of-range rows and columns hold the ghost extrapolations, so every
 // in-plane neighbour is a constant LDS offset.
-template <typename T, int D, class Ham, int STAGE, int RS>
+template <typename T, int D, class Ham, int STAGE, int RS, int ORDER>
 __device__ uint64_t tile_plane(const ProbDesc& P, const ProbState& S, int64_t tile, T* lds)
 {
     const T* __restrict__ in = (const T*)(STAGE == 1 ? P.V : P.Vhat);
@@ -441,9 +436,12 @@ __device__ uint64_t tile_plane(const ProbDesc& P, const ProbState& S, int64_t ti
     // ---- stencil ----
     Ham ham;
     ham.init(P);
-    const T* ah = Prec<T>::ah(S);
+    // per-problem coefficients in registers (through a pointer the
+    // compiler would reload them after every store)
+    T ah[4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) ah[a] = Prec<T>::ah(S)[a];
     const T dt = Prec<T>::dt(S);
-    const int order = P.order;
     const bool edge0 = D == 4 && (i0 < 2 || i0 > P.n[0] - 3);
     const bool edge1 = D == 4 && (i1 < 2 || i1 > P.n[1] - 3);
     uint64_t rmax = 0;
@@ -471,21 +469,21 @@ __device__ uint64_t tile_plane(const ProbDesc& P, const ProbState& S, int64_t ti
             const T* q = lds + (rr + 2) * RS + cc + 2;
             const T c = q[0];
             T sum[4], dif;
-            eno_sum_dif<T>(q[-2 * RS], q[-RS], c, q[RS], q[2 * RS], order, sum[ra], dif);
+            eno_sd<T, ORDER>(q[-2 * RS], q[-RS], c, q[RS], q[2 * RS], sum[ra], dif);
             T L = ah[ra] * dif;
-            eno_sum_dif<T>(q[-2], q[-1], c, q[1], q[2], order, sum[ca], dif);
+            eno_sd<T, ORDER>(q[-2], q[-1], c, q[1], q[2], sum[ca], dif);
             L += ah[ca] * dif;
             if (D == 4) {
                 T m2 = w[0], m1 = w[1], p1 = w[2], p2 = w[3];
                 if (edge0) ghost_fix<T>(i0, P.n[0], c, m2, m1, p1, p2);
-                eno_sum_dif<T>(m2, m1, c, p1, p2, order, sum[0], dif);
+                eno_sd<T, ORDER>(m2, m1, c, p1, p2, sum[0], dif);
                 L += ah[0] * dif;
                 m2 = w[4];
                 m1 = w[5];
                 p1 = w[6];
                 p2 = w[7];
                 if (edge1) ghost_fix<T>(i1, P.n[1], c, m2, m1, p1, p2);
-                eno_sum_dif<T>(m2, m1, c, p1, p2, order, sum[1], dif);
+                eno_sd<T, ORDER>(m2, m1, c, p1, p2, sum[1], dif);
                 L += ah[1] * dif;
                 L += ham(sum, i0, i1, r0 + rr, cc);
             } else {
@@ -510,14 +508,23 @@ template <typename T, int STAGE>
 __device__ __forceinline__ uint64_t run_tile(const ProbDesc& P, const ProbState& S, int64_t tile,
                                              T* lds)
 {
+    const bool o1 = P.order == 1;
     switch (P.kind) {
     case HJR_QUAD_Z2D:
-        if (P.path == kPathPlaneS) return tile_plane<T, 2, HamZ2D<T>, STAGE, kRowStrideS>(P, S, tile, lds);
-        if (P.path == kPathPlaneL) return tile_plane<T, 2, HamZ2D<T>, STAGE, kRowStrideL>(P, S, tile, lds);
+        if (P.path == kPathPlaneS)
+            return o1 ? tile_plane<T, 2, HamZ2D<T>, STAGE, kRowStrideS, 1>(P, S, tile, lds)
+                      : tile_plane<T, 2, HamZ2D<T>, STAGE, kRowStrideS, 2>(P, S, tile, lds);
+        if (P.path == kPathPlaneL)
+            return o1 ? tile_plane<T, 2, HamZ2D<T>, STAGE, kRowStrideL, 1>(P, S, tile, lds)
+                      : tile_plane<T, 2, HamZ2D<T>, STAGE, kRowStrideL, 2>(P, S, tile, lds);
         return tile_flat<T, 2, HamZ2D<T>, STAGE>(P, S, tile);
     case HJR_QUAD_X4D:
-        if (P.path == kPathPlaneS) return tile_plane<T, 4, HamX4D<T>, STAGE, kRowStrideS>(P, S, tile, lds);
-        if (P.path == kPathPlaneL) return tile_plane<T, 4, HamX4D<T>, STAGE, kRowStrideL>(P, S, tile, lds);
+        if (P.path == kPathPlaneS)
+            return o1 ? tile_plane<T, 4, HamX4D<T>, STAGE, kRowStrideS, 1>(P, S, tile, lds)
+                      : tile_plane<T, 4, HamX4D<T>, STAGE, kRowStrideS, 2>(P, S, tile, lds);
+        if (P.path == kPathPlaneL)
+            return o1 ? tile_plane<T, 4, HamX4D<T>, STAGE, kRowStrideL, 1>(P, S, tile, lds)
+                      : tile_plane<T, 4, HamX4D<T>, STAGE, kRowStrideL, 2>(P, S, tile, lds);
         return tile_flat<T, 4, HamX4D<T>, STAGE>(P, S, tile);
     case HJR_DI2X2:
         return tile_flat<T, 4, HamDI2X2<T>, STAGE>(P, S, tile);
