@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "warm"])
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "warm", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk", type=int, default=0)
@@ -166,7 +166,7 @@ def mode_step(args, torch, hjr, W):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic("stage2"),
             "bytes_per_cell_update": 16,
             "avg_launch_us": kms[1] / max(kn[1], 1) * 1e3,
             "launches": int(kn[1]),
@@ -300,6 +300,49 @@ def mode_warm(args, torch, hjr, W):
     return out
 
 
+# ---------------------------------------------------------------------------
+# copy mode: a plain device copy of known size, to calibrate the HBM byte
+# counters (FETCH_SIZE / WRITE_SIZE) that rocprofv3 reports for the kernels
+# ---------------------------------------------------------------------------
+
+def mode_copy(args, torch, hjr, W):
+    nbytes = 256 << 20
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(4):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    return {"mode": "copy", "bytes_per_copy": nbytes, "copies": 4}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_stage_decomposed_quad10d.json")
+KERNEL_SOURCES = ["hjr_stencil.hpp", "hjr_kernels.hip", "hjr_device.hpp", "hjr_engine.cpp"]
+
+
+def kernel_hash():
+    """Hash of the sources that define the stage kernels and their tiles."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2101_05916_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage_key):
+    """HBM bytes per launch from the committed rocprofv3 counters, or None
+    when the kernel sources changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get(stage_key, {}).get("traffic_bytes_per_launch")
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -313,7 +356,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     hjr.lib()
-    fn = {"step": mode_step, "batch": mode_batch, "serve": mode_serve, "warm": mode_warm}[args.mode]
+    fn = {"step": mode_step, "batch": mode_batch, "serve": mode_serve, "warm": mode_warm,
+          "copy": mode_copy}[args.mode]
     out = fn(args, torch, hjr, W)
     print(json.dumps(out), flush=True)
 
