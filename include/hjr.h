@@ -116,13 +116,18 @@ typedef struct hjr_opts {
     int32_t chunk;          /* iterations enqueued between host convergence
                                checks; 0 = library default */
     int32_t flags;          /* HJR_FLAG_* */
+    int32_t tile_rows;      /* rows of the two fastest axes per LDS tile (a
+                               tuning knob, see paper_2101_05916_amd/autotune.py);
+                               0 = library default.  Clamped to what fits. */
+    int32_t reserved;
 } hjr_opts;
 
 /* flags */
 #define HJR_FLAG_NO_GRAPH 1     /* launch chunks kernel by kernel, no hipGraph */
 #define HJR_FLAG_NO_PIPELINE 2  /* wait for each chunk before enqueuing the next */
-#define HJR_FLAG_PROFILE 4      /* time every RK-stage kernel with HIP events
-                                   (implies HJR_FLAG_NO_GRAPH) */
+#define HJR_FLAG_PROFILE 4      /* time the RK-stage launches of one chunk in
+                                   eight with HIP events (implies
+                                   HJR_FLAG_NO_GRAPH) */
 #define HJR_FLAG_FLAT_TILES 8   /* use the shape-agnostic flat tiles only (the
                                    LDS plane tiles are the default where the
                                    last axis has <= 204 nodes) */
@@ -138,8 +143,10 @@ typedef struct hjr_stats {
     int64_t cell_updates;   /* sum over levels of (nodes x steps) */
     double device_ms;       /* device time from the first enqueue to completion */
     double kernel_ms[2];    /* with HJR_FLAG_PROFILE: summed device time of the
-                               RK stage-1 and stage-2 kernels of the call */
-    int64_t kernel_launches[2]; /* with HJR_FLAG_PROFILE: their launch counts */
+                               timed RK stage-1 and stage-2 launches */
+    int64_t kernel_launches[2]; /* with HJR_FLAG_PROFILE: number of timed launches */
+    int64_t kernel_cell_updates; /* with HJR_FLAG_PROFILE: cell-updates those timed
+                                    launches performed */
 } hjr_stats;
 
 /* Fill *o with the defaults listed in hjr_opts.  Never fails for o != NULL. */
@@ -224,6 +231,7 @@ typedef struct hjr_problem {
     const void* V0;         /* start on level 0, NULL = cold */
     hjr_dstb d[2];
     double tol;
+    int32_t tile_rows[4];   /* per level, 0 = hjr_opts.tile_rows / default */
 } hjr_problem;
 
 /* Bytes of device workspace hjr_solve_batch needs for these problems. */

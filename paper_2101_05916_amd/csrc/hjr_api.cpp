@@ -42,6 +42,7 @@ bool opts_valid(const hjr_opts& o)
     if (!(o.cfl > 0.0 && o.cfl <= 1.0)) return false;
     if (o.max_iter < 1) return false;
     if (o.chunk < 0 || o.chunk > kMaxChunk) return false;
+    if (o.tile_rows < 0) return false;
     return true;
 }
 
@@ -199,7 +200,7 @@ void fill_stats(hjr_stats* st, const Job& j, const ProbState& ps, double ms, con
         if (k < j.nlev) cu += grid_size(j.lev[k].grid) * j.level_iters[k];
     }
     st->cell_updates = cu;
-    eng.profile(st->kernel_ms, st->kernel_launches);
+    eng.profile(st->kernel_ms, st->kernel_launches, &st->kernel_cell_updates);
     st->iterations = tot;
     st->residual = j.residual;
     st->dt = ps.dt;
@@ -314,6 +315,7 @@ hjr_status hjr_solve_levels(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* gr
             j.lev[k].l = l[k];
             j.lev[k].V = V_levels[k];
             j.lev[k].mask = masks ? masks[k] : nullptr;
+            j.lev[k].tile_rows = op.tile_rows;
         }
         j.V0 = V0;
         int64_t Nmax = 0;
@@ -424,6 +426,7 @@ hjr_status hjr_solve_batch(int32_t n, const hjr_problem* probs, const hjr_opts* 
                 j.lev[k].l = pr.l[k];
                 j.lev[k].V = pr.V[k];
                 j.lev[k].mask = nullptr;
+                j.lev[k].tile_rows = pr.tile_rows[k] > 0 ? pr.tile_rows[k] : op.tile_rows;
                 Nmax = std::max(Nmax, grid_size(pr.grids[k]));
             }
             j.V0 = pr.V0;

@@ -23,6 +23,7 @@ constexpr int kNodesPerThread = 512 / HJR_STAGE_BLOCK > 1 ? 512 / HJR_STAGE_BLOC
 constexpr int kTile = kStageBlock * kNodesPerThread;  // nodes per flat tile
 constexpr int kResSubs = 64;         // residual atomics spread over 64 words
 constexpr int kMaxChunk = 256;       // iterations per chunk, upper bound
+constexpr int kProfileEvery = 8;     // HJR_FLAG_PROFILE times one chunk in this many
 
 // Plane tiles: one workgroup stages the two fastest axes of a tile in LDS
 // with a row stride fixed at compile time, so every in-plane neighbour is a

@@ -230,6 +230,8 @@ hjr_status Engine::reset(const EngineCfg& c)
     table_dirty_ = true;
     prof_ms_[0] = prof_ms_[1] = 0.0;
     prof_n_[0] = prof_n_[1] = 0;
+    prof_cells_ = 0;
+    chunk_ = 0;  // profiling samples chunks 0, kProfileEvery, ... of every call
     HJR_TRY(launch_fill_u64(stream_, d_mask_counts_, 4 * (int64_t)cfg_.cap, 0));
     return HJR_OK;
 }
@@ -325,6 +327,7 @@ void Engine::fill_desc(const Job* j, ProbDesc& P) const
             // staged elements per thread, and the LDS block within kPlaneElems
             int want = std::min(kPlaneElems / rs - 4, kPlaneNodesPT * kStageBlock / nc);
             want = std::min(want, kPlaneStagePT * kStageBlock / nc - 4);
+            if (L.tile_rows > 0) want = std::min(want, L.tile_rows);
             want = std::max(want, 1);
             const int chunks = (nr + want - 1) / want;
             P.rows = (nr + chunks - 1) / chunks;
@@ -420,15 +423,15 @@ ChunkArgs Engine::args(int par, int slot) const
     return a;
 }
 
-hjr_status Engine::enqueue_chunk_body(int par)
+hjr_status Engine::enqueue_chunk_body(int par, bool timed)
 {
     HJR_TRY(launch_prologue(stream_, args(par, 0)));
     for (int s = 0; s < cfg_.K; s++) {
         const ChunkArgs a = args(par, s);
         for (int stage = 1; stage <= 2; stage++) {
-            if (profile_) HJR_TRY(hipEventRecord(prof_ev_[par][4 * s + 2 * (stage - 1)], stream_));
+            if (timed) HJR_TRY(hipEventRecord(prof_ev_[par][4 * s + 2 * (stage - 1)], stream_));
             HJR_TRY(launch_stage(stream_, cfg_.dtype, stage, a, geff_));
-            if (profile_) HJR_TRY(hipEventRecord(prof_ev_[par][4 * s + 2 * (stage - 1) + 1], stream_));
+            if (timed) HJR_TRY(hipEventRecord(prof_ev_[par][4 * s + 2 * (stage - 1) + 1], stream_));
         }
     }
     HJR_TRY(launch_epilogue(stream_, args(par, 0)));
@@ -439,7 +442,7 @@ hjr_status Engine::build_graph(int par, hipGraphExec_t* out)
 {
     hipGraph_t g = nullptr;
     HJR_TRY(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-    hjr_status st = enqueue_chunk_body(par);
+    hjr_status st = enqueue_chunk_body(par, false);
     hipError_t e = hipStreamEndCapture(stream_, &g);
     if (st != HJR_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -500,7 +503,11 @@ hjr_status Engine::step()
         }
         HJR_TRY(hipGraphLaunch(ge, stream_));
     } else {
-        hjr_status st = enqueue_chunk_body(par);
+        // with HJR_FLAG_PROFILE one chunk in kProfileEvery is timed launch by
+        // launch: events between kernels cost throughput, so the sample keeps
+        // the rest of the run undisturbed
+        f.timed = profile_ && (chunk_ % kProfileEvery == 0);
+        hjr_status st = enqueue_chunk_body(par, f.timed);
         if (st != HJR_OK) return st;
     }
     HJR_TRY(hipMemcpyAsync(h_compact_[par], d_compact_[par], sizeof(double) * (size_t)cap * K,
@@ -541,7 +548,7 @@ hjr_status Engine::process(Flight& f)
     const int par = (int)(f.chunk & 1);
     const double* r = h_compact_[par];
     const int K = cfg_.K;
-    if (profile_)
+    if (f.timed)
         for (int s = 0; s < K; s++)
             for (int st = 0; st < 2; st++) {
                 float ms = 0.f;
@@ -562,6 +569,7 @@ hjr_status Engine::process(Flight& f)
                 hit = k;
                 break;
             }
+        if (f.timed) prof_cells_ += grid_size(j->lev[j->cur].grid) * (hit >= 0 ? hit + 1 : lim);
         if (hit >= 0) {
             finish_level(j, HJR_OK, f.sched[s] + hit + 1, rs[hit]);
         } else if (f.sched[s] + lim >= cfg_.max_iter) {

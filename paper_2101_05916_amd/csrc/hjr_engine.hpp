@@ -39,6 +39,7 @@ struct Level {
     const void* l = nullptr;
     void* V = nullptr;
     uint8_t* mask = nullptr;  // optional refinement-mask output
+    int tile_rows = 0;        // LDS tile height, 0 = default
 };
 
 // One solve job: a chain of 1..4 grid levels of one subsystem.
@@ -104,12 +105,13 @@ public:
 
     // Summed device time (ms) and launch count of the stage-1 / stage-2
     // kernels, with HJR_FLAG_PROFILE.
-    void profile(double ms[2], int64_t n[2]) const
+    void profile(double ms[2], int64_t n[2], int64_t* cells) const
     {
         for (int i = 0; i < 2; i++) {
             ms[i] = prof_ms_[i];
             n[i] = prof_n_[i];
         }
+        *cells = prof_cells_;
     }
 
     hipStream_t stream() const { return stream_; }
@@ -120,6 +122,7 @@ private:
     struct Flight {
         int64_t chunk;
         hipEvent_t ev;
+        bool timed = false;         // stage launches bracketed by events
         std::vector<Job*> job;      // per slot, job that ran (or null)
         std::vector<int> limit;     // per slot
         std::vector<int64_t> sched; // per slot, steps scheduled before this chunk
@@ -127,7 +130,7 @@ private:
 
     hjr_status setup_level(Job* j);
     hjr_status upload_table();
-    hjr_status enqueue_chunk_body(int par);
+    hjr_status enqueue_chunk_body(int par, bool timed);
     hjr_status build_graph(int par, hipGraphExec_t* out);
     hjr_status process(Flight& f);
     void finish_level(Job* j, int status, int64_t iters, double residual);
@@ -172,6 +175,7 @@ private:
     std::vector<hipEvent_t> prof_ev_[2];
     double prof_ms_[2] = {0.0, 0.0};
     int64_t prof_n_[2] = {0, 0};
+    int64_t prof_cells_ = 0;  // cell-updates done by the timed launches
 };
 
 // Helpers shared by the API layer and the server.

@@ -51,7 +51,8 @@ class Dstb(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("order", C.c_int32), ("cfl", C.c_double),
                 ("max_iter", C.c_int64), ("stream", C.c_void_p), ("workspace", C.c_void_p),
-                ("workspace_bytes", C.c_size_t), ("chunk", C.c_int32), ("flags", C.c_int32)]
+                ("workspace_bytes", C.c_size_t), ("chunk", C.c_int32), ("flags", C.c_int32),
+                ("tile_rows", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -59,20 +60,22 @@ class Stats(C.Structure):
                 ("alpha", C.c_double * 4), ("status", C.c_int32), ("levels", C.c_int32),
                 ("level_iterations", C.c_int64 * 4), ("cell_updates", C.c_int64),
                 ("device_ms", C.c_double), ("kernel_ms", C.c_double * 2),
-                ("kernel_launches", C.c_int64 * 2)]
+                ("kernel_launches", C.c_int64 * 2), ("kernel_cell_updates", C.c_int64)]
 
     def as_dict(self) -> dict:
         return dict(iterations=self.iterations, residual=self.residual, dt=self.dt,
                     alpha=list(self.alpha), status=self.status, levels=self.levels,
                     level_iterations=list(self.level_iterations),
                     cell_updates=self.cell_updates, device_ms=self.device_ms,
-                    kernel_ms=list(self.kernel_ms), kernel_launches=list(self.kernel_launches))
+                    kernel_ms=list(self.kernel_ms), kernel_launches=list(self.kernel_launches),
+                    kernel_cell_updates=self.kernel_cell_updates)
 
 
 class Problem(C.Structure):
     _fields_ = [("dyn", Dyn), ("nlev", C.c_int32), ("reserved", C.c_int32),
                 ("grids", Grid * 4), ("l", C.c_void_p * 4), ("V", C.c_void_p * 4),
-                ("V0", C.c_void_p), ("d", Dstb * 2), ("tol", C.c_double)]
+                ("V0", C.c_void_p), ("d", Dstb * 2), ("tol", C.c_double),
+                ("tile_rows", C.c_int32 * 4)]
 
 
 class ServerCfg(C.Structure):
@@ -200,7 +203,8 @@ def _dtype_code(dtype) -> int:
     raise ValueError(f"unsupported dtype {dtype}")
 
 
-def make_opts(dtype=None, order=2, cfl=0.8, max_iter=100000, chunk=0, flags=0, stream=None) -> Opts:
+def make_opts(dtype=None, order=2, cfl=0.8, max_iter=100000, chunk=0, flags=0, stream=None,
+              tile_rows=0) -> Opts:
     torch = _torch()
     o = Opts()
     lib().hjr_opts_default(C.byref(o))
@@ -210,6 +214,7 @@ def make_opts(dtype=None, order=2, cfl=0.8, max_iter=100000, chunk=0, flags=0, s
     o.max_iter = max_iter
     o.chunk = chunk
     o.flags = flags
+    o.tile_rows = tile_rows
     if stream is None:
         stream = torch.cuda.current_stream()
     o.stream = C.c_void_p(stream.cuda_stream)
@@ -269,7 +274,7 @@ def workspace_bytes(spec: Spec, opts: Opts) -> int:
 
 
 def solve(spec: Spec, l, V0=None, V_out=None, *, dtype=None, order=2, cfl=0.8,
-          max_iter=100000, chunk=0, flags=0, workspace=True, check=True):
+          max_iter=100000, chunk=0, flags=0, workspace=True, check=True, tile_rows=0):
     """One safe-set solve.  l, V0, V_out: device tensors of spec.size elements.
     Returns (V_out, stats dict).  Raises HjrError on failure; a solve that
     hits max_iter returns with stats['status'] == NOT_CONVERGED."""
@@ -282,7 +287,7 @@ def solve(spec: Spec, l, V0=None, V_out=None, *, dtype=None, order=2, cfl=0.8,
     if V_out is None:
         V_out = torch.empty(N, dtype=dtype, device=l.device)
     _check_tensor(V_out, N, dtype, "V_out")
-    o = make_opts(dtype, order, cfl, max_iter, chunk, flags)
+    o = make_opts(dtype, order, cfl, max_iter, chunk, flags, tile_rows=tile_rows)
     ws = None
     if workspace:
         nb = workspace_bytes(spec, o)
@@ -336,7 +341,7 @@ def solve_levels(spec: Spec, grids_n, ls, V0=None, *, dtype=None, order=2, cfl=0
     return Vs, mk, (list(counts) if masks else None), out
 
 
-def make_problem(spec: Spec, l, V_out, V0=None, levels=None) -> Problem:
+def make_problem(spec: Spec, l, V_out, V0=None, levels=None, tile_rows=None) -> Problem:
     """levels: optional list of (n, l_k, V_k) for a coarse-to-fine job; else
     one level with (spec.n, l, V_out)."""
     p = Problem()
@@ -353,6 +358,8 @@ def make_problem(spec: Spec, l, V_out, V0=None, levels=None) -> Problem:
     p.d[0] = dd[0]
     p.d[1] = dd[1]
     p.tol = spec.tol
+    for k, r in enumerate(tile_rows or []):
+        p.tile_rows[k] = int(r)
     return p
 
 
