@@ -18,6 +18,12 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #ifndef HJR_PLANE_NODES_PT
 #define HJR_PLANE_NODES_PT 8
 #endif
+#ifndef HJR_NODE_UNROLL
+#define HJR_NODE_UNROLL 2            // nodes of a lane whose loads are issued together
+#endif
+#ifndef HJR_WAVES_PER_EU
+#define HJR_WAVES_PER_EU 0           // occupancy hint for the stage kernels, 0 = none
+#endif
 constexpr int kStageBlock = HJR_STAGE_BLOCK;
 constexpr int kNodesPerThread = 512 / HJR_STAGE_BLOCK > 1 ? 512 / HJR_STAGE_BLOCK : 2;  // nodes per thread of a flat tile
 constexpr int kTile = kStageBlock * kNodesPerThread;  // nodes per flat tile

@@ -101,8 +101,14 @@ __device__ __forceinline__ void flush_residual(const ChunkArgs& A, int p, uint64
     }
 }
 
+#if HJR_WAVES_PER_EU > 0
+#define HJR_STAGE_ATTR __attribute__((amdgpu_waves_per_eu(HJR_WAVES_PER_EU, 8)))
+#else
+#define HJR_STAGE_ATTR
+#endif
+
 template <typename T, int STAGE>
-__global__ __launch_bounds__(kStageBlock) void k_stage(ChunkArgs A)
+__global__ __launch_bounds__(kStageBlock) HJR_STAGE_ATTR void k_stage(ChunkArgs A)
 {
     __shared__ uint64_t red[kStageBlock / 64];
     __shared__ __align__(16) char smem[kPlaneElems * sizeof(T)];

@@ -446,7 +446,7 @@ __device__ uint64_t tile_plane(const ProbDesc& P, const ProbState& S, int64_t ti
     const bool edge1 = D == 4 && (i1 < 2 || i1 > P.n[1] - 3);
     uint64_t rmax = 0;
     // nodes two at a time: the global loads of a pair are issued together
-#pragma unroll 2
+#pragma unroll HJR_NODE_UNROLL
     for (int k = 0; k < kPlaneNodesPT; k++) {
         const int e = tid + k * kStageBlock;
         if (e < cnt) {
