@@ -51,6 +51,10 @@ def parse():
     return ap.parse_args()
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
 
@@ -198,10 +202,12 @@ def mode_batch(args, torch, hjr, W):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     cu_plain = 0
-    for P, l, V in keep:
+    for i, (P, l, V) in enumerate(keep):
         _, st = hjr.solve(hjr.Spec.of(P), l, V_out=V, flags=hjr.FLAG_NO_GRAPH | hjr.FLAG_NO_PIPELINE,
                           chunk=1)
         cu_plain += st["cell_updates"]
+        if i % 32 == 31:
+            progress(f"plain {i + 1}/{len(keep)} solves, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     V_plain = [V.clone() for _, _, V in keep]
@@ -213,9 +219,12 @@ def mode_batch(args, torch, hjr, W):
     t_batch = time.perf_counter() - t0
     cu = sum(s["cell_updates"] for s in stats)
     same = all(torch.equal(a, V) for a, (_, _, V) in zip(V_plain, keep))
+    conv = sum(1 for s in stats if s["status"] == 0)
+    n4 = sum(1 for P, _, _ in keep if P.ndim == 4)
     return {
         "metric": "safe-set updates/s (batched vs plain)", "mode": "batch",
-        "problems": len(keep), "dtype": "f32", "data": "synthetic",
+        "problems": len(keep), "problems_4d": n4, "converged": conv,
+        "tol": W.TOL, "band_4d": W.BAND_4D_UPDATE, "dtype": "f32", "data": "synthetic",
         "plain": {"seconds": t_plain, "updates_per_s": len(keep) / t_plain,
                   "cell_updates_per_s": cu_plain / t_plain},
         "batched": {"seconds": t_batch, "updates_per_s": len(keep) / t_batch,
@@ -234,7 +243,8 @@ def mode_serve(args, torch, hjr, W):
     specs = {}
     ls = {}
     for I in insts:
-        P = W.quad_x4d(I["n"]) if I["kind"] == W.QUAD_X4D else W.quad_z2d(I["n"])
+        P = (W.quad_x4d(I["n"], band=I["band"]) if I["kind"] == W.QUAD_X4D
+             else W.quad_z2d(I["n"]))
         specs[I["instance"]] = P
         ls[I["instance"]] = P.l.astype(np.float32)
     srv = hjr.Server(hbm_budget_bytes=8 << 30, max_active=64, chunk=args.chunk or 16)
@@ -251,7 +261,12 @@ def mode_serve(args, torch, hjr, W):
         first = r["instance"] not in seen
         seen.add(r["instance"])
         tickets.append((r, srv.submit(r["instance"], spec, ls[r["instance"]] if first else None)))
-    replies = [(r, srv.wait(t)) for r, t in tickets]
+    progress(f"submitted {len(tickets)} requests in {time.perf_counter() - t0:.1f} s")
+    replies = []
+    for i, (r, t) in enumerate(tickets):
+        replies.append((r, srv.wait(t)))
+        if i % 500 == 499:
+            progress(f"{i + 1} replies, {time.perf_counter() - t0:.1f} s")
     wall = time.perf_counter() - t0
     used, budget = srv.memory()
     srv.close()
@@ -274,33 +289,55 @@ def mode_serve(args, torch, hjr, W):
 # ---------------------------------------------------------------------------
 
 def mode_warm(args, torch, hjr, W):
-    def dev(P):
-        return torch.tensor(P.l, dtype=torch.float32, device="cuda")
+    """Warm start and coarse-to-fine on the 4-D x-subsystem: the initial
+    safe set at dbar 0.5 (21^4 -> 41^4 -> 61^4), then the update to dbar 0.8
+    four ways: cold 61^4 (the baseline), cold coarse-to-fine, warm at 61^4
+    from the previous value, and the previous value restricted to 21^4,
+    warm there, then refined to 41^4 and 61^4."""
+    band = W.BAND_4D_UPDATE
+    sizes = (21, 41, 61)
+    P5 = [W.quad_x4d(n, 0.5, band=band) for n in sizes]
+    ls = [torch.tensor(P.l, dtype=torch.float32, device="cuda") for P in P5]
+    ns = [P.n for P in P5]
+    nodes = [P.size for P in P5]
+    spec5 = hjr.Spec.of(P5[-1])
+    spec8 = hjr.Spec.of(W.quad_x4d(61, 0.8, band=band))
+    mi = 30000
+    out = {"metric": "iterations and time: warm / coarse-to-fine vs cold", "mode": "warm",
+           "tol": W.TOL, "band": band, "dtype": "f32", "max_iter": mi}
 
-    P21, P41, P61 = W.quad_x4d(21, 0.5), W.quad_x4d(41, 0.5), W.quad_x4d(61, 0.5)
-    spec5 = hjr.Spec.of(P61)
-    ls = [dev(P21), dev(P41), dev(P61)]
-    out = {"metric": "iterations and time: warm / coarse-to-fine vs cold", "mode": "warm"}
+    def rec(name, its, secs, status, V):
+        its = [int(i) for i in its]
+        cu = sum(i * nodes[len(nodes) - len(its) + k] for k, i in enumerate(its))
+        out[name] = {"level_iterations": its, "cell_updates": cu, "seconds": secs,
+                     "status": int(status)}
+        progress(f"{name}: {its} in {secs:.2f} s")
+        return V
+
     t0 = time.perf_counter()
-    Vs, _, _, st = hjr.solve_levels(spec5, [P21.n, P41.n, P61.n], ls)
-    out["initial_coarse_to_fine"] = {"levels": st["level_iterations"][:3],
-                                     "seconds": time.perf_counter() - t0}
-    V61 = Vs[-1]
-    spec8 = hjr.Spec.of(W.quad_x4d(61, 0.8))
+    Vs, _, _, st = hjr.solve_levels(spec5, ns, ls, max_iter=mi)
+    V61 = rec("initial_coarse_to_fine", st["level_iterations"][:3], time.perf_counter() - t0,
+              st["status"], Vs[-1])
     t0 = time.perf_counter()
-    Vc, stc = hjr.solve(spec8, ls[2])
-    out["update_cold_61"] = {"iterations": stc["iterations"], "seconds": time.perf_counter() - t0}
+    Vc, s = hjr.solve(spec8, ls[2], max_iter=mi)
+    rec("update_cold_61", [s["iterations"]], time.perf_counter() - t0, s["status"], Vc)
     t0 = time.perf_counter()
-    Vw, stw = hjr.solve(spec8, ls[2], V0=V61)
-    out["update_warm_61"] = {"iterations": stw["iterations"], "seconds": time.perf_counter() - t0}
+    Vs1, _, _, s = hjr.solve_levels(spec8, ns, ls, max_iter=mi)
+    rec("update_cold_coarse_to_fine", s["level_iterations"][:3], time.perf_counter() - t0,
+        s["status"], Vs1[-1])
     t0 = time.perf_counter()
-    V21 = hjr.interp(P61.n, V61, P21.n, P61.lo, P61.hi)
-    Vs2, _, _, st2 = hjr.solve_levels(spec8, [P21.n, P41.n, P61.n], ls, V0=V21)
-    out["update_restrict_warm_coarse_to_fine"] = {"levels": st2["level_iterations"][:3],
-                                                  "seconds": time.perf_counter() - t0}
-    a, b = Vc.cpu().numpy(), Vw.cpu().numpy()
-    out["warm_vs_cold_zero_level_disagreement"] = float(np.mean((a >= 0) != (b >= 0)))
-    out["c2f_vs_cold_zero_level_disagreement"] = float(np.mean((a >= 0) != (Vs2[-1].cpu().numpy() >= 0)))
+    Vw, s = hjr.solve(spec8, ls[2], V0=V61, max_iter=mi)
+    rec("update_warm_61", [s["iterations"]], time.perf_counter() - t0, s["status"], Vw)
+    t0 = time.perf_counter()
+    V21 = hjr.interp(ns[2], V61, ns[0], P5[2].lo, P5[2].hi)
+    Vs2, _, _, s = hjr.solve_levels(spec8, ns, ls, V0=V21, max_iter=mi)
+    rec("update_restrict_warm_coarse_to_fine", s["level_iterations"][:3],
+        time.perf_counter() - t0, s["status"], Vs2[-1])
+    cold = Vc.cpu().numpy() >= 0
+    for name, V in (("update_cold_coarse_to_fine", Vs1[-1]), ("update_warm_61", Vw),
+                    ("update_restrict_warm_coarse_to_fine", Vs2[-1])):
+        out[name]["zero_level_disagreement_vs_cold_61"] = float(
+            np.mean((V.cpu().numpy() >= 0) != cold))
     return out
 
 

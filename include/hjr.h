@@ -17,8 +17,11 @@
  *     one-sided derivatives (two linear-extrapolation ghost nodes per side),
  *     alpha_i = max over the grid and the control/disturbance box vertices of
  *     |f_i| (global Lax-Friedrichs), dt = cfl / sum_i alpha_i / dx_i.  The
- *     iteration stops after the first step whose max |V' - V| over all nodes
- *     is < tol.  The safe set is { V >= 0 }.
+ *     iteration stops after the first step whose residual max |V' - V| is
+ *     < tol; the residual runs over all nodes, or, with a band b > 0, over
+ *     the nodes where |V| < b or |V'| < b (the safe set { V >= 0 } depends
+ *     on the values near V = 0 only; the paper asks for convergence without
+ *     fixing a norm).
  *   - Sec. III-A: a decomposable system is solved as independent subsystem
  *     problems (hjr_solve_batch solves many in one device pass).
  *   - Sec. III-B: warm start -- pass a previous converged V as V0.
@@ -120,6 +123,8 @@ typedef struct hjr_opts {
                                tuning knob, see paper_2101_05916_amd/autotune.py);
                                0 = library default.  Clamped to what fits. */
     int32_t reserved;
+    double band;            /* residual band of the stop test (see above);
+                               0 (default) = every node; must be >= 0 */
 } hjr_opts;
 
 /* flags */
@@ -169,7 +174,8 @@ hjr_status hjr_workspace_bytes(const hjr_grid* g, const hjr_opts* o, size_t* out
  *   V0          initial value, or NULL for the cold start V0 = l; the first
  *               iterate is min(l, V0).  May alias V_out (in-place update).
  *   d           host array of disturbance bounds, one per channel of dyn
- *   tol         > 0; stop after the first step with max |V' - V| < tol
+ *   tol         > 0; stop after the first step whose residual (max |V' - V|
+ *               over the nodes selected by o->band) is < tol
  *   o           options (NULL = defaults)
  *   V_out       result (N elements); holds the last iterate on NOT_CONVERGED
  *   iterations, residual   host outputs (nullable)
@@ -232,6 +238,8 @@ typedef struct hjr_problem {
     hjr_dstb d[2];
     double tol;
     int32_t tile_rows[4];   /* per level, 0 = hjr_opts.tile_rows / default */
+    double band;            /* residual band of this problem's stop test,
+                               0 = every node (hjr_opts.band is not used) */
 } hjr_problem;
 
 /* Bytes of device workspace hjr_solve_batch needs for these problems. */
@@ -281,6 +289,7 @@ typedef struct hjr_request {
     double tol;
     int32_t cold;             /* 1 = ignore the resident value, start from l */
     int32_t reserved;
+    double band;              /* residual band of the stop test, 0 = every node */
 } hjr_request;
 
 typedef struct hjr_reply {

@@ -428,15 +428,27 @@ double orc_iterate_at(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
     }
 }
 
+double orc_residual_band(int64_t N, const double* V, const double* Vnew, double band)
+{
+    double r = 0.0;
+    for (int64_t i = 0; i < N; i++) {
+        if (band > 0.0 && fabs(V[i]) >= band && fabs(Vnew[i]) >= band) continue;
+        double diff = fabs(Vnew[i] - V[i]);
+        if (!(diff <= r)) r = diff; /* a NaN difference propagates */
+    }
+    return r;
+}
+
 int orc_solve(const orc_dyn* dyn, const orc_grid* g, const double* l,
               const double* V0, const double* dlo, const double* dhi,
-              double tol, double cfl, int order, int64_t max_iter,
+              double tol, double band, double cfl, int order, int64_t max_iter,
               double* V_out, int64_t* iterations, double* residual,
               double* dt_out, double* alpha_out, double* res_hist,
               double* max_rise)
 {
     if (!grid_valid(g) || orc_state_dim(dyn->kind) != g->ndim) return ORC_EINVAL;
     if (!(tol > 0.0) || !(cfl > 0.0 && cfl <= 1.0) || max_iter < 1) return ORC_EINVAL;
+    if (!(band >= 0.0)) return ORC_EINVAL;
     if (order != 1 && order != 2) return ORC_EINVAL;
     for (int c = 0; c < orc_num_dstb(dyn->kind); c++)
         if (!(dlo[c] <= dhi[c])) return ORC_EINVAL;
@@ -462,6 +474,7 @@ int orc_solve(const orc_dyn* dyn, const orc_grid* g, const double* l,
     double r = 0.0;
     for (k = 0; k < max_iter; k++) {
         r = orc_iterate(dyn, g, dlo, dhi, alpha, dt, order, l, V, Vn);
+        if (band > 0.0) r = orc_residual_band(N, V, Vn, band);
         if (max_rise)
             for (int64_t i = 0; i < N; i++)
                 if (Vn[i] - V[i] > rise) rise = Vn[i] - V[i];

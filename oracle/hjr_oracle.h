@@ -113,7 +113,15 @@ double orc_iterate_at(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
                       int order, const double* l, const double* V,
                       int64_t idx);
 
-/* Time-marched solve of the variational inequality until max|dV| < tol.
+/* Residual of one iteration, max |Vnew - V|, over the nodes near the zero
+ * level set: node i is left out only if both |V[i]| >= band and
+ * |Vnew[i]| >= band.  band == 0 counts every node.  A NaN value is always
+ * counted, and a NaN difference makes the result NaN.  (A narrow-band stop
+ * rule: the safe set { V >= 0 } depends on the values near V = 0 only.) */
+double orc_residual_band(int64_t N, const double* V, const double* Vnew, double band);
+
+/* Time-marched solve of the variational inequality until the residual of an
+ * iteration (orc_residual_band with the given band; 0 = all nodes) < tol.
  *   V0 == NULL: cold start V0 = l.  Otherwise V <- min(l, V0) (warm start).
  *   res_hist (nullable, length max_iter): residual of every iteration.
  *   max_rise (nullable): max over iterations and nodes of V_{k+1} - V_k.
@@ -121,7 +129,7 @@ double orc_iterate_at(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
  * ORC_EINVAL. */
 int orc_solve(const orc_dyn* dyn, const orc_grid* g, const double* l,
               const double* V0, const double* dlo, const double* dhi,
-              double tol, double cfl, int order, int64_t max_iter,
+              double tol, double band, double cfl, int order, int64_t max_iter,
               double* V_out, int64_t* iterations, double* residual,
               double* dt_out, double* alpha_out, double* res_hist,
               double* max_rise);

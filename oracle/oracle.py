@@ -75,8 +75,11 @@ def lib():
         L.orc_iterate_at.argtypes = [yp, gp, dp, dp, dp, C.c_double, C.c_int, dp, dp,
                                      C.c_int64]
         L.orc_solve.restype = C.c_int
-        L.orc_solve.argtypes = [yp, gp, dp, dp, dp, dp, C.c_double, C.c_double, C.c_int,
-                                C.c_int64, dp, C.POINTER(C.c_int64), dp, dp, dp, dp, dp]
+        L.orc_solve.argtypes = [yp, gp, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
+                                C.c_int, C.c_int64, dp, C.POINTER(C.c_int64), dp, dp, dp,
+                                dp, dp]
+        L.orc_residual_band.restype = C.c_double
+        L.orc_residual_band.argtypes = [C.c_int64, dp, dp, C.c_double]
         L.orc_interp.restype = C.c_int
         L.orc_interp.argtypes = [gp, dp, gp, dp]
         L.orc_refine_mask.restype = C.c_int64
@@ -191,9 +194,16 @@ def iterate_at(dyn, grid, dlo, dhi, alpha, dt_, l, V, idx, order=2) -> float:
                                 dt_, order, _dp(l), _dp(V), int(idx))
 
 
+def residual_band(V, Vnew, band):
+    V, Vnew = _f64(V), _f64(Vnew)
+    return lib().orc_residual_band(V.size, _dp(V), _dp(Vnew), float(band))
+
+
 def solve(dyn, grid, l, dlo, dhi, tol=1e-4, V0=None, cfl=0.8, order=2,
-          max_iter=100000, history=False):
-    """Returns dict(V, status, iterations, residual, dt, alpha, res_hist, max_rise)."""
+          max_iter=100000, history=False, band=0.0):
+    """Returns dict(V, status, iterations, residual, dt, alpha, res_hist, max_rise).
+    band > 0 restricts the stop test to nodes with |V| < band before or after
+    the step (see orc_residual_band)."""
     l = _f64(l)
     lo, hi = _dbounds(dlo, dhi)
     V = np.zeros_like(l)
@@ -208,7 +218,7 @@ def solve(dyn, grid, l, dlo, dhi, tol=1e-4, V0=None, cfl=0.8, order=2,
         V0 = _f64(V0)
         v0p = _dp(V0)
     st = lib().orc_solve(C.byref(dyn), C.byref(grid), _dp(l), v0p, _dp(lo), _dp(hi),
-                         float(tol), float(cfl), int(order), int(max_iter), _dp(V),
+                         float(tol), float(band), float(cfl), int(order), int(max_iter), _dp(V),
                          C.byref(it), C.byref(res), C.byref(dt_), _dp(a),
                          _dp(hist) if history else None, C.byref(rise))
     out = dict(V=V, status=st, iterations=it.value, residual=res.value, dt=dt_.value,

@@ -43,6 +43,7 @@ bool opts_valid(const hjr_opts& o)
     if (o.max_iter < 1) return false;
     if (o.chunk < 0 || o.chunk > kMaxChunk) return false;
     if (o.tile_rows < 0) return false;
+    if (!(o.band >= 0.0)) return false;
     return true;
 }
 
@@ -223,8 +224,9 @@ hjr_status run_engine(Engine& eng)
 }
 
 hjr_status check_job_spec(const hjr_dyn* dyn, int nlev, const hjr_grid* grids, const hjr_dstb* d,
-                          double tol)
+                          double tol, double band)
 {
+    if (!(band >= 0.0)) return HJR_EINVAL;  // negative or NaN
     if (!dyn || !grids || !d) return HJR_EINVAL;
     if (nlev < 1 || nlev > 4) return HJR_EINVAL;
     for (int k = 0; k < nlev; k++) {
@@ -284,7 +286,7 @@ hjr_status hjr_solve_levels(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* gr
 {
     const hjr_opts op = resolve(o);
     if (!opts_valid(op)) return HJR_EINVAL;
-    hjr_status st = check_job_spec(dyn, nlev, grids, d, tol);
+    hjr_status st = check_job_spec(dyn, nlev, grids, d, tol, op.band);
     if (st != HJR_OK) return st;
     if (!l || !V_levels) return HJR_EINVAL;
     for (int k = 0; k < nlev; k++)
@@ -309,6 +311,7 @@ hjr_status hjr_solve_levels(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* gr
         std::memset(j.d, 0, sizeof(j.d));
         for (int c = 0; c < dyn_channels(dyn->kind); c++) j.d[c] = d[c];
         j.tol = tol;
+        j.band = op.band;
         j.nlev = nlev;
         for (int k = 0; k < nlev; k++) {
             j.lev[k].grid = grids[k];
@@ -389,7 +392,7 @@ hjr_status hjr_solve_batch(int32_t n, const hjr_problem* probs, const hjr_opts* 
     if (!opts_valid(op) || n < 1 || !probs) return HJR_EINVAL;
     for (int i = 0; i < n; i++) {
         const hjr_problem& p = probs[i];
-        hjr_status st = check_job_spec(&p.dyn, p.nlev, p.grids, p.d, p.tol);
+        hjr_status st = check_job_spec(&p.dyn, p.nlev, p.grids, p.d, p.tol, p.band);
         if (st != HJR_OK) return st;
         for (int k = 0; k < p.nlev; k++)
             if (!p.l[k] || !p.V[k]) return HJR_EINVAL;
@@ -419,6 +422,7 @@ hjr_status hjr_solve_batch(int32_t n, const hjr_problem* probs, const hjr_opts* 
             std::memset(j.d, 0, sizeof(j.d));
             for (int c = 0; c < dyn_channels(pr.dyn.kind); c++) j.d[c] = pr.d[c];
             j.tol = pr.tol;
+            j.band = pr.band;
             j.nlev = pr.nlev;
             int64_t Nmax = 0;
             for (int k = 0; k < pr.nlev; k++) {

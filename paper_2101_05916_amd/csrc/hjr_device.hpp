@@ -81,6 +81,7 @@ struct ProbDesc {
     double dlo[2];
     double dhi[2];
     double tol;
+    double band;             // residual counts nodes with |V| < band or |V'| < band (+inf = all)
     double cfl;
     void* V;                 // value, updated in place
     const void* l;           // constraint

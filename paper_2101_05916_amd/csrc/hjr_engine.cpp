@@ -267,6 +267,7 @@ void Engine::fill_desc(const Job* j, ProbDesc& P) const
         P.dhi[c] = j->d[c].hi;
     }
     P.tol = j->tol;
+    P.band = j->band > 0.0 ? j->band : HUGE_VAL;
     P.cfl = cfg_.cfl;
     P.V = L.V;
     P.l = L.l;

@@ -48,6 +48,7 @@ struct Job {
     hjr_dyn dyn;
     hjr_dstb d[2];
     double tol = 1e-4;
+    double band = 0.0;         // residual band, 0 = every node
     int nlev = 1;
     Level lev[4];
     const void* V0 = nullptr;  // start of level 0 (nullptr = cold)

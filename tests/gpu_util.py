@@ -18,7 +18,7 @@ def odyn(P):
 
 def oracle_solve(P, V0=None, max_iter=100000, order=2, history=False, l=None):
     return O.solve(odyn(P), ogrid(P), P.l if l is None else l, P.dlo, P.dhi, tol=P.tol,
-                   V0=V0, order=order, max_iter=max_iter, history=history)
+                   V0=V0, order=order, max_iter=max_iter, history=history, band=P.band)
 
 
 def device_solve(P, dtype, V0=None, max_iter=100000, order=2, flags=0, chunk=0, l_host=None):

@@ -94,7 +94,8 @@ def test_workspace_bytes():
 
 
 @pytest.mark.parametrize("what", ["n<3", "lo>=hi", "ndim", "tol", "cfl", "order", "dstb",
-                                  "kind", "null_l", "theta_range", "max_iter", "perm"])
+                                  "kind", "null_l", "theta_range", "max_iter", "perm",
+                                  "band<0", "band_nan"])
 def test_solve_rejects_invalid_arguments_without_device(what):
     """Every one of these returns EINVAL before any HIP call (no GPU here)."""
     L = hjr.lib()
@@ -126,6 +127,10 @@ def test_solve_rejects_invalid_arguments_without_device(what):
         n, lo, hi = [11] * 4, [-5, -2, -2.0, -2], [5, 2, 2.0, 2]
     elif what == "max_iter":
         kw = dict(max_iter=0)
+    elif what == "band<0":
+        kw = dict(band=-0.5)
+    elif what == "band_nan":
+        kw = dict(band=float("nan"))
     elif what == "perm":
         kind = hjr.DI2X2
         params = (0.91, 9.81, 7, 16, 0.91, 9.81, 7, 16, 0, 1, 1, 3)

@@ -44,8 +44,9 @@ def single(P, dtype=torch.float32, V0=None, **kw):
 
 
 def mixed_problems():
-    return [W.quad_x4d(21, 0.5, "x"), W.quad_x4d(17, 0.8, "y"), W.quad_z2d(101, 0.5, "z"),
-            W.quad_z2d(51, 0.3, "z2"), W.quad_x4d((9, 13, 11, 15), 0.6, "r")]
+    return [W.quad_x4d(21, 0.5, "x"), W.quad_x4d(17, 0.8, "y", band=0.5),
+            W.quad_z2d(101, 0.5, "z"), W.quad_z2d(51, 0.3, "z2"),
+            W.quad_x4d((9, 13, 11, 15), 0.6, "r")]
 
 
 @pytest.mark.parametrize("flags", [0, 1, 2])
@@ -202,7 +203,8 @@ def server_reference(reqs, specs, ls):
 
 
 def make_instances():
-    specs = {0: W.quad_z2d(51), 1: W.quad_z2d(101), 2: W.quad_x4d(17), 3: W.quad_x4d(21)}
+    specs = {0: W.quad_z2d(51), 1: W.quad_z2d(101), 2: W.quad_x4d(17),
+             3: W.quad_x4d(21, band=W.BAND_4D_UPDATE)}
     return specs, {k: dev(P.l) for k, P in specs.items()}
 
 

@@ -76,6 +76,32 @@ def test_z2d_fp32_full_solve(n, dbar):
     assert dis <= 1e-3
 
 
+# ---------------------------------------------------------------- narrow-band stop rule
+
+@pytest.mark.parametrize("case", ["x4d13_f64", "x4d13_f32", "z2d101_f64"])
+def test_band_full_solve(case):
+    """Stop test over the band |V| < 0.5: the device stops at the oracle's
+    step (13^4 has ragged LDS tiles; the band cuts 1175 steps to 410)."""
+    kind, dt = case.split("_")
+    P = W.quad_x4d(13, 0.5, band=0.5) if kind == "x4d13" else W.quad_z2d(101, 0.5)
+    if kind == "z2d101":
+        P.band = 0.5
+    ref = oracle_solve(P, history=True)
+    V, st = device_solve(P, torch.float64 if dt == "f64" else torch.float32)
+    err = float(np.max(np.abs(V - ref["V"])))
+    dis = zero_level_disagreement(V, ref["V"])
+    print(f"{case} band 0.5: it {st['iterations']} vs {ref['iterations']}, max|dV| {err:.3e}, "
+          f"zero-level disagreement {dis:.2e}")
+    assert st["status"] == 0 and ref["status"] == 0
+    if dt == "f64":
+        assert st["iterations"] == ref["iterations"]
+        assert err <= FP64_TOL
+    else:
+        assert iterations_match(st["iterations"], ref)
+        assert err <= 1e-4
+        assert dis <= 1e-3
+
+
 # ---------------------------------------------------------------- 4-D, fixed step counts
 
 def _x4d_fixed(n, dtype, steps, dbar=0.5):
