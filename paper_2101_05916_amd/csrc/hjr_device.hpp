@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/hjr.h"
+
 namespace hjr {
 
 constexpr int kBlock = 256;          // threads per workgroup of the utility kernels
@@ -25,6 +27,14 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #define HJR_WAVES_PER_EU 0           // occupancy hint for the stage kernels, 0 = none
 #endif
 constexpr int kStageBlock = HJR_STAGE_BLOCK;
+#ifndef HJR_NODE_UNROLL1
+#define HJR_NODE_UNROLL1 HJR_NODE_UNROLL
+#endif
+#ifndef HJR_NODE_UNROLL2
+#define HJR_NODE_UNROLL2 HJR_NODE_UNROLL
+#endif
+constexpr int kNodeUnroll1 = HJR_NODE_UNROLL1;  // plane-tile node unroll, stage 1
+constexpr int kNodeUnroll2 = HJR_NODE_UNROLL2;  // and stage 2
 constexpr int kNodesPerThread = 512 / HJR_STAGE_BLOCK > 1 ? 512 / HJR_STAGE_BLOCK : 2;  // nodes per thread of a flat tile
 constexpr int kTile = kStageBlock * kNodesPerThread;  // nodes per flat tile
 constexpr int kResSubs = 64;         // residual atomics spread over 64 words
@@ -33,14 +43,47 @@ constexpr int kProfileEvery = 8;     // HJR_FLAG_PROFILE times one chunk in this
 
 // Plane tiles: one workgroup stages the two fastest axes of a tile in LDS
 // with a row stride fixed at compile time, so every in-plane neighbour is a
-// constant LDS offset.  kPlaneElems bounds (rows + 4) * stride.
+// constant LDS offset.  plane_elems(stride) bounds (rows + 4) * stride.
 constexpr int kRowStrideS = 72;      // planes whose last axis has <= 68 nodes
 constexpr int kRowStrideL = 208;     // planes whose last axis has <= 204 nodes
 constexpr int kPlaneNodesPT = HJR_PLANE_NODES_PT;   // nodes per thread of a plane tile
 constexpr int kPlaneStagePT = 2 * kPlaneNodesPT;    // staged elements per thread of a plane tile
-constexpr int kPlaneElems = kPlaneStagePT * kStageBlock + 4 * kRowStrideL;  // LDS elements of one block
+constexpr int kPlaneElemsS = 18 * kRowStrideS;  // LDS elements of a narrow block (<= 14 rows)
+constexpr int kPlaneElemsL = 8 * kRowStrideL;   // LDS elements of a wide block (<= 4 rows)
 
 enum TilePath : int32_t { kPathFlat = 0, kPathPlaneS = 1, kPathPlaneL = 2 };
+
+// Tile families.  Every family has its own stage kernels, so registers and
+// LDS are sized for its tile code alone; a chunk launches one kernel per
+// family present.  Plane families are (model, row stride, ENO order).
+enum Family : int32_t {
+    kFamFlat = 0,
+    kFamZ2dS2, kFamZ2dL2, kFamX4dS2, kFamX4dL2,
+    kFamZ2dS1, kFamZ2dL1, kFamX4dS1, kFamX4dL1,
+    kNumFam
+};
+
+__host__ __device__ constexpr int fam_rs(int f)
+{
+    return (f == kFamZ2dS2 || f == kFamX4dS2 || f == kFamZ2dS1 || f == kFamX4dS1) ? kRowStrideS
+         : (f == kFamFlat) ? 0 : kRowStrideL;
+}
+
+__host__ __device__ constexpr int fam_order(int f)
+{
+    return (f >= kFamZ2dS1) ? 1 : 2;
+}
+
+__host__ __device__ constexpr bool fam_x4d(int f)
+{
+    return f == kFamX4dS2 || f == kFamX4dL2 || f == kFamX4dS1 || f == kFamX4dL1;
+}
+
+// LDS elements of a plane block of row stride rs (0 for flat tiles).
+__host__ __device__ constexpr int plane_elems(int rs)
+{
+    return rs == kRowStrideS ? kPlaneElemsS : rs == kRowStrideL ? kPlaneElemsL : 0;
+}
 
 // Division of a 31-bit unsigned index by a runtime divisor d >= 2 with one
 // 32x32->hi multiply: q = mulhi(x, m) >> s, with s = ceil(log2 d) - 1 and
@@ -91,6 +134,15 @@ struct ProbDesc {
     int64_t ntiles;
 };
 
+// Family of a problem's tiles (its model, tile path and ENO order).
+inline int family_of(const ProbDesc& P)
+{
+    if (P.path == kPathFlat) return kFamFlat;
+    const bool narrow = P.path == kPathPlaneS, x4 = P.kind == HJR_QUAD_X4D;
+    const int base = P.order == 1 ? kFamZ2dS1 : kFamZ2dS2;  // Z2D S, Z2D L, X4D S, X4D L
+    return base + (x4 ? 2 : 0) + (narrow ? 0 : 1);
+}
+
 // Device-written per-problem quantities (once per level).
 struct ProbState {
     uint64_t alpha_bits[4];  // max-reduction of |f_i| as IEEE bit patterns
@@ -105,11 +157,17 @@ struct ProbState {
 };
 
 // Per-chunk header and per-problem control (written by the host each chunk).
+// The tiles of family f are [fam_tile[f], fam_tile[f+1]); its problems sit at
+// positions [fam_pos[f], fam_pos[f+1]) of the order list (ChunkArgs::ord),
+// with first tiles ChunkArgs::tb, increasing.
 struct ChunkHdr {
     int64_t total_tiles;
     int32_t nprob;
     int32_t pad;
+    int64_t fam_tile[kNumFam + 1];
+    int32_t fam_pos[kNumFam + 1];
 };
+static_assert(sizeof(ChunkHdr) <= 256, "ChunkHdr must fit its 256-byte slot");
 
 struct ProbCtl {
     int32_t limit;   // iterations this problem may take in this chunk (0..K)
@@ -119,6 +177,8 @@ struct ProbCtl {
 // Kernel argument block for the iteration kernels.
 struct ChunkArgs {
     const ProbDesc* probs;
+    const int64_t* tb;   // first tile of the problem at each order position
+    const int32_t* ord;  // problem slot at each order position
     ProbState* states;
     const ChunkHdr* hdr;
     const ProbCtl* ctl;

@@ -146,7 +146,7 @@ size_t Engine::table_bytes(int cap, int K)
 {
     if (K > kMaxChunk) K = kMaxChunk;
     size_t b = 0;
-    b += align256(sizeof(ProbDesc) * cap);
+    b += align256((sizeof(ProbDesc) + sizeof(int64_t) + sizeof(int32_t)) * cap);
     b += align256(sizeof(ProbState) * cap);
     b += 2 * align256(256 + sizeof(ProbCtl) * cap);
     b += 2 * align256(sizeof(uint64_t) * (size_t)cap * (K + 1) * kResSubs);
@@ -172,7 +172,10 @@ hjr_status Engine::init(hipStream_t stream, void* arena)
         p += align256(bytes);
         return (void*)r;
     };
-    d_desc_ = (ProbDesc*)take(sizeof(ProbDesc) * cap);
+    desc_bytes_ = (sizeof(ProbDesc) + sizeof(int64_t) + sizeof(int32_t)) * cap;
+    d_desc_ = (ProbDesc*)take(desc_bytes_);
+    d_tb_ = (int64_t*)(d_desc_ + cap);
+    d_ord_ = (int32_t*)(d_tb_ + cap);
     d_state_ = (ProbState*)take(sizeof(ProbState) * cap);
     ctl_bytes_ = 256 + sizeof(ProbCtl) * cap;
     for (int q = 0; q < 2; q++) {
@@ -184,11 +187,11 @@ hjr_status Engine::init(hipStream_t stream, void* arena)
     d_mask_counts_ = (uint64_t*)take(sizeof(uint64_t) * 4 * cap);
 
     for (int q = 0; q < 2; q++) {
-        HJR_TRY(hipHostMalloc((void**)&h_desc_[q], sizeof(ProbDesc) * cap, hipHostMallocDefault));
+        HJR_TRY(hipHostMalloc((void**)&h_desc_[q], desc_bytes_, hipHostMallocDefault));
         HJR_TRY(hipHostMalloc((void**)&h_ctl_[q], ctl_bytes_, hipHostMallocDefault));
         HJR_TRY(hipHostMalloc((void**)&h_compact_[q], sizeof(double) * (size_t)cap * K,
                               hipHostMallocDefault));
-        std::memset(h_desc_[q], 0, sizeof(ProbDesc) * cap);
+        std::memset(h_desc_[q], 0, desc_bytes_);
         std::memset(h_ctl_[q], 0, ctl_bytes_);
         HJR_TRY(hipEventCreateWithFlags(&desc_ev_[q], hipEventDisableTiming));
         HJR_TRY(hipEventRecord(desc_ev_[q], stream_));
@@ -198,15 +201,14 @@ hjr_status Engine::init(hipStream_t stream, void* arena)
         HJR_TRY(launch_fill_u64(stream_, (uint64_t*)d_compact_[q], (int64_t)cap * K, 0));
     HJR_TRY(launch_fill_u64(stream_, d_mask_counts_, 4 * (int64_t)cap, 0));
 
-    if (cfg_.grid > 0) {
-        grid_ = cfg_.grid;
-    } else {
-        int dev = 0, cus = 0;
-        HJR_TRY(hipGetDevice(&dev));
-        HJR_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        grid_ = cus * stage_blocks_per_cu(cfg_.dtype);
-    }
-    grid_ = std::max(8, (grid_ + 7) / 8 * 8);
+    int dev = 0, cus = 0;
+    HJR_TRY(hipGetDevice(&dev));
+    HJR_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    for (int st = 0; st < 2; st++)
+        for (int f = 0; f < kNumFam; f++) {
+            int g = cfg_.grid > 0 ? cfg_.grid : cus * stage_blocks_per_cu(cfg_.dtype, st + 1, f);
+            fam_grid_[st][f] = std::max(8, (g + 7) / 8 * 8);
+        }
     if (profile_)
         for (int q = 0; q < 2; q++) {
             prof_ev_[q].resize(4 * (size_t)K);
@@ -325,8 +327,8 @@ void Engine::fill_desc(const Job* j, ProbDesc& P) const
         }
         if (rs) {
             // rows per tile: at most kPlaneNodesPT nodes and kPlaneStagePT
-            // staged elements per thread, and the LDS block within kPlaneElems
-            int want = std::min(kPlaneElems / rs - 4, kPlaneNodesPT * kStageBlock / nc);
+            // staged elements per thread, and the LDS block within plane_elems
+            int want = std::min(plane_elems(rs) / rs - 4, kPlaneNodesPT * kStageBlock / nc);
             want = std::min(want, kPlaneStagePT * kStageBlock / nc - 4);
             if (L.tile_rows > 0) want = std::min(want, L.tile_rows);
             want = std::max(want, 1);
@@ -386,22 +388,41 @@ hjr_status Engine::upload_table()
     const int q = desc_par_;
     desc_par_ ^= 1;
     HJR_TRY(hipEventSynchronize(desc_ev_[q]));  // staging q no longer being read
+    const int cap = cfg_.cap;
     ProbDesc* h = h_desc_[q];
-    int64_t total = 0;
-    for (int s = 0; s < cfg_.cap; s++) {
+    int64_t* tb = (int64_t*)(h + cap);
+    int32_t* ord = (int32_t*)(tb + cap);
+    std::vector<int> fam_of(cap, -1);
+    for (int s = 0; s < cap; s++) {
         Job* j = slots_[s];
         if (j && !j->done) {
             fill_desc(j, h[s]);
+            if (h[s].ntiles > 0) fam_of[s] = family_of(h[s]);
         } else {
             std::memset(&h[s], 0, sizeof(ProbDesc));
             h[s].tol = 1.0;
             h[s].ntiles = 0;
         }
-        h[s].tile_begin = total;
-        total += h[s].ntiles;
     }
+    // tiles grouped by family, problems in slot order within a family
+    int64_t total = 0;
+    int pos = 0;
+    for (int f = 0; f < kNumFam; f++) {
+        fam_tile_[f] = total;
+        fam_pos_[f] = pos;
+        for (int s = 0; s < cap; s++) {
+            if (fam_of[s] != f) continue;
+            h[s].tile_begin = total;
+            tb[pos] = total;
+            ord[pos] = s;
+            pos++;
+            total += h[s].ntiles;
+        }
+    }
+    fam_tile_[kNumFam] = total;
+    fam_pos_[kNumFam] = pos;
     total_tiles_ = total;
-    HJR_TRY(hipMemcpyAsync(d_desc_, h, sizeof(ProbDesc) * cfg_.cap, hipMemcpyHostToDevice, stream_));
+    HJR_TRY(hipMemcpyAsync(d_desc_, h, desc_bytes_, hipMemcpyHostToDevice, stream_));
     HJR_TRY(hipEventRecord(desc_ev_[q], stream_));
     table_dirty_ = false;
     return HJR_OK;
@@ -411,6 +432,8 @@ ChunkArgs Engine::args(int par, int slot) const
 {
     ChunkArgs a;
     a.probs = d_desc_;
+    a.tb = d_tb_;
+    a.ord = d_ord_;
     a.states = d_state_;
     a.hdr = d_hdr_[par];
     a.ctl = d_ctl_[par];
@@ -431,7 +454,8 @@ hjr_status Engine::enqueue_chunk_body(int par, bool timed)
         const ChunkArgs a = args(par, s);
         for (int stage = 1; stage <= 2; stage++) {
             if (timed) HJR_TRY(hipEventRecord(prof_ev_[par][4 * s + 2 * (stage - 1)], stream_));
-            HJR_TRY(launch_stage(stream_, cfg_.dtype, stage, a, geff_));
+            for (const Launch& l : launches_)
+                HJR_TRY(launch_stage(stream_, cfg_.dtype, stage, l.fam, a, l.grid[stage - 1]));
             if (timed) HJR_TRY(hipEventRecord(prof_ev_[par][4 * s + 2 * (stage - 1) + 1], stream_));
         }
     }
@@ -473,6 +497,10 @@ hjr_status Engine::step()
     ProbCtl* ctl = (ProbCtl*)(h_ctl_[par] + 256);
     hdr->total_tiles = total_tiles_;
     hdr->nprob = cap;
+    for (int f = 0; f <= kNumFam; f++) {
+        hdr->fam_tile[f] = fam_tile_[f];
+        hdr->fam_pos[f] = fam_pos_[f];
+    }
     for (int s = 0; s < cap; s++) {
         Job* j = slots_[s];
         ctl[s].limit = 0;
@@ -490,17 +518,26 @@ hjr_status Engine::step()
         }
     }
     HJR_TRY(hipMemcpyAsync(d_hdr_[par], h_ctl_[par], ctl_bytes_, hipMemcpyHostToDevice, stream_));
-    // launch no more workgroups than there are tiles (a multiple of 8, so
-    // that every XCD gets its share)
-    geff_ = (int)std::min<int64_t>(grid_, std::max<int64_t>(8, (total_tiles_ + 7) / 8 * 8));
+    // one launch per family present, with no more workgroups than it has
+    // tiles (a multiple of 8, so that every XCD gets its share)
+    launches_.clear();
+    for (int fm = 0; fm < kNumFam; fm++) {
+        const int64_t nt = fam_tile_[fm + 1] - fam_tile_[fm];
+        if (nt <= 0) continue;
+        Launch l;
+        l.fam = fm;
+        for (int st = 0; st < 2; st++)
+            l.grid[st] = (int)std::min<int64_t>(fam_grid_[st][fm], std::max<int64_t>(8, (nt + 7) / 8 * 8));
+        launches_.push_back(l);
+    }
     if (use_graph_) {
         hipGraphExec_t ge = nullptr;
         for (auto& g : graphs_[par])
-            if (g.first == geff_) ge = g.second;
+            if (g.first == launches_) ge = g.second;
         if (!ge) {
             hjr_status st = build_graph(par, &ge);
             if (st != HJR_OK) return st;
-            graphs_[par].push_back({geff_, ge});
+            graphs_[par].push_back({launches_, ge});
         }
         HJR_TRY(hipGraphLaunch(ge, stream_));
     } else {

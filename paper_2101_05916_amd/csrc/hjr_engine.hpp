@@ -117,7 +117,6 @@ public:
 
     hipStream_t stream() const { return stream_; }
     const EngineCfg& cfg() const { return cfg_; }
-    int grid() const { return grid_; }
 
 private:
     struct Flight {
@@ -138,30 +137,46 @@ private:
     void fill_desc(const Job* j, ProbDesc& P) const;
     ChunkArgs args(int par, int slot) const;
 
+    // Stage launches of the current chunk: family and workgroups per stage.
+    struct Launch {
+        int fam;
+        int grid[2];
+        bool operator==(const Launch& o) const
+        {
+            return fam == o.fam && grid[0] == o.grid[0] && grid[1] == o.grid[1];
+        }
+    };
+
     EngineCfg cfg_;
     hipStream_t stream_ = nullptr;
-    int grid_ = 0;
+    int fam_grid_[2][kNumFam] = {};  // workgroup cap per stage and family (occupancy x CUs)
     bool own_arena_ = false;
     void* arena_ = nullptr;
-    // device tables
+    // device tables: problem descriptors, then the family order list (first
+    // tile per position, slot per position)
     ProbDesc* d_desc_ = nullptr;
+    int64_t* d_tb_ = nullptr;
+    int32_t* d_ord_ = nullptr;
+    size_t desc_bytes_ = 0;
     ProbState* d_state_ = nullptr;
     ChunkHdr* d_hdr_[2] = {nullptr, nullptr};
     ProbCtl* d_ctl_[2] = {nullptr, nullptr};
     uint64_t* d_res_[2] = {nullptr, nullptr};
     double* d_compact_[2] = {nullptr, nullptr};
     uint64_t* d_mask_counts_ = nullptr;  // [cap][4]
-    // pinned host mirrors
+    // pinned host mirrors (descriptors + order list, one copy)
     ProbDesc* h_desc_[2] = {nullptr, nullptr};
     hipEvent_t desc_ev_[2] = {nullptr, nullptr};
     int desc_par_ = 0;
     char* h_ctl_[2] = {nullptr, nullptr};      // ChunkHdr then cap x ProbCtl
     double* h_compact_[2] = {nullptr, nullptr};
     size_t ctl_bytes_ = 0;
-    // graphs, per buffer parity and launch grid size
-    std::vector<std::pair<int, hipGraphExec_t>> graphs_[2];
+    // graphs, per buffer parity and launch list
+    std::vector<std::pair<std::vector<Launch>, hipGraphExec_t>> graphs_[2];
     bool use_graph_ = false;
-    int geff_ = 8;  // workgroups of the iteration kernels in the current chunk
+    std::vector<Launch> launches_;  // stage launches of the current chunk
+    int64_t fam_tile_[kNumFam + 1] = {};
+    int32_t fam_pos_[kNumFam + 1] = {};
     // bookkeeping
     std::vector<Job*> slots_;
     int running_ = 0;

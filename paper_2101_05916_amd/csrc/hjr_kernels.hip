@@ -58,15 +58,14 @@ __device__ uint64_t block_max_u64(uint64_t v, uint64_t* red)
     return r;
 }
 
-// Problem owning global tile t: the last p with tile_begin <= t (binary
-// search; tile_begin is non-decreasing over the table, and a problem without
-// tiles shares its tile_begin with the next one, which therefore wins).
-__device__ __forceinline__ int find_prob(const ProbDesc* probs, int nprob, int64_t t)
+// Order position owning tile t among positions [lo, hi) of a family: the
+// last one whose first tile is <= t (first tiles increase along the order).
+__device__ __forceinline__ int find_pos(const int64_t* tb, int lo, int hi, int64_t t)
 {
-    int lo = 0, hi = nprob - 1;
+    hi -= 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (probs[mid].tile_begin <= t)
+        if (tb[mid] <= t)
             lo = mid;
         else
             hi = mid - 1;
@@ -107,32 +106,40 @@ __device__ __forceinline__ void flush_residual(const ChunkArgs& A, int p, uint64
 #define HJR_STAGE_ATTR
 #endif
 
-template <typename T, int STAGE>
+// One RK stage over the tiles of family FAM.  The family's tiles are split
+// into eight contiguous ranges, one per XCD (workgroup b runs on XCD b mod
+// 8), and the workgroups of an XCD stride through its range.
+template <typename T, int STAGE, int FAM>
 __global__ __launch_bounds__(kStageBlock) HJR_STAGE_ATTR void k_stage(ChunkArgs A)
 {
+    constexpr int kElems = FAM == kFamFlat ? 4 : plane_elems(fam_rs(FAM)) + kStageBlock;
     __shared__ uint64_t red[kStageBlock / 64];
-    __shared__ __align__(16) char smem[kPlaneElems * sizeof(T)];
+    __shared__ __align__(16) char smem[kElems * sizeof(T)];
     T* lds = (T*)smem;
-    const int64_t total = A.hdr->total_tiles;
-    const int nprob = A.hdr->nprob;
+    const int pb = A.hdr->fam_pos[FAM], pe = A.hdr->fam_pos[FAM + 1];
+    if (pb >= pe) return;
+    const int64_t t0 = A.hdr->fam_tile[FAM], t1 = A.hdr->fam_tile[FAM + 1];
+    const int64_t total = t1 - t0;
     const int G8 = (int)gridDim.x >> 3;
     const int xcd = (int)blockIdx.x & 7;
     const int local = (int)blockIdx.x >> 3;
-    const int64_t beg = total * xcd / 8, end = total * (xcd + 1) / 8;
+    const int64_t beg = t0 + total * xcd / 8, end = t0 + total * (xcd + 1) / 8;
     int cur = -1;
+    int64_t lo = 0, hi = 0;  // tile range of the current problem
     bool active = false;
     uint64_t rmax = 0;
     for (int64_t t = beg + local; t < end; t += G8) {
-        const int p = find_prob(A.probs, nprob, t);
-        if (p != cur) {
+        if (t >= hi || t < lo) {
+            const int pos = find_pos(A.tb, pb, pe, t);
             if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red);
-            cur = p;
+            cur = A.ord[pos];
+            lo = A.tb[pos];
+            hi = pos + 1 < pe ? A.tb[pos + 1] : t1;
             rmax = 0;
-            active = prob_active(A, p);
+            active = prob_active(A, cur);
         }
         if (!active) continue;
-        const ProbDesc& P = A.probs[p];
-        rmax = umax64(rmax, run_tile<T, STAGE>(P, A.states[p], t - P.tile_begin, lds));
+        rmax = umax64(rmax, run_tile<T, STAGE, FAM>(A.probs[cur], A.states[cur], (uint32_t)(t - lo), lds));
     }
     if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red);
 }
@@ -425,20 +432,32 @@ hipError_t launch_epilogue(hipStream_t s, const ChunkArgs& a)
     return hipGetLastError();
 }
 
-hipError_t launch_stage(hipStream_t s, int dtype, int stage, const ChunkArgs& a, int grid)
+template <typename T, int STAGE>
+static hipError_t launch_stage_t(hipStream_t s, int fam, const ChunkArgs& a, int grid)
 {
-    if (dtype == HJR_F32) {
-        if (stage == 1)
-            hipLaunchKernelGGL((k_stage<float, 1>), dim3(grid), dim3(kStageBlock), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_stage<float, 2>), dim3(grid), dim3(kStageBlock), 0, s, a);
-    } else {
-        if (stage == 1)
-            hipLaunchKernelGGL((k_stage<double, 1>), dim3(grid), dim3(kStageBlock), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_stage<double, 2>), dim3(grid), dim3(kStageBlock), 0, s, a);
+    const dim3 g(grid), b(kStageBlock);
+    switch (fam) {
+    case kFamFlat: hipLaunchKernelGGL((k_stage<T, STAGE, kFamFlat>), g, b, 0, s, a); break;
+    case kFamZ2dS2: hipLaunchKernelGGL((k_stage<T, STAGE, kFamZ2dS2>), g, b, 0, s, a); break;
+    case kFamZ2dL2: hipLaunchKernelGGL((k_stage<T, STAGE, kFamZ2dL2>), g, b, 0, s, a); break;
+    case kFamX4dS2: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dS2>), g, b, 0, s, a); break;
+    case kFamX4dL2: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dL2>), g, b, 0, s, a); break;
+    case kFamZ2dS1: hipLaunchKernelGGL((k_stage<T, STAGE, kFamZ2dS1>), g, b, 0, s, a); break;
+    case kFamZ2dL1: hipLaunchKernelGGL((k_stage<T, STAGE, kFamZ2dL1>), g, b, 0, s, a); break;
+    case kFamX4dS1: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dS1>), g, b, 0, s, a); break;
+    case kFamX4dL1: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dL1>), g, b, 0, s, a); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_stage(hipStream_t s, int dtype, int stage, int fam, const ChunkArgs& a, int grid)
+{
+    if (dtype == HJR_F32)
+        return stage == 1 ? launch_stage_t<float, 1>(s, fam, a, grid)
+                          : launch_stage_t<float, 2>(s, fam, a, grid);
+    return stage == 1 ? launch_stage_t<double, 1>(s, fam, a, grid)
+                      : launch_stage_t<double, 2>(s, fam, a, grid);
 }
 
 hipError_t launch_level_setup(hipStream_t s, int dtype, const ProbDesc& P, ProbState* st)
@@ -529,14 +548,28 @@ hipError_t launch_fill_u64(hipStream_t s, uint64_t* p, int64_t n, uint64_t value
     return hipGetLastError();
 }
 
-int stage_blocks_per_cu(int dtype)
+template <typename T, int STAGE>
+static const void* stage_kernel(int fam)
 {
+    switch (fam) {
+    case kFamFlat: return (const void*)k_stage<T, STAGE, kFamFlat>;
+    case kFamZ2dS2: return (const void*)k_stage<T, STAGE, kFamZ2dS2>;
+    case kFamZ2dL2: return (const void*)k_stage<T, STAGE, kFamZ2dL2>;
+    case kFamX4dS2: return (const void*)k_stage<T, STAGE, kFamX4dS2>;
+    case kFamX4dL2: return (const void*)k_stage<T, STAGE, kFamX4dL2>;
+    case kFamZ2dS1: return (const void*)k_stage<T, STAGE, kFamZ2dS1>;
+    case kFamZ2dL1: return (const void*)k_stage<T, STAGE, kFamZ2dL1>;
+    case kFamX4dS1: return (const void*)k_stage<T, STAGE, kFamX4dS1>;
+    default: return (const void*)k_stage<T, STAGE, kFamX4dL1>;
+    }
+}
+
+int stage_blocks_per_cu(int dtype, int stage, int fam)
+{
+    const void* k = dtype == HJR_F32 ? (stage == 1 ? stage_kernel<float, 1>(fam) : stage_kernel<float, 2>(fam))
+                                     : (stage == 1 ? stage_kernel<double, 1>(fam) : stage_kernel<double, 2>(fam));
     int n = 0;
-    hipError_t e;
-    if (dtype == HJR_F32)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_stage<float, 2>, kStageBlock, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_stage<double, 2>, kStageBlock, 0);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kStageBlock, 0);
     if (e != hipSuccess || n < 1) n = 2;
     return n;
 }

@@ -10,7 +10,8 @@ namespace hjr {
 
 // Iteration kernels (one chunk = prologue, K x (stage 1, stage 2), epilogue).
 hipError_t launch_prologue(hipStream_t s, const ChunkArgs& a);
-hipError_t launch_stage(hipStream_t s, int dtype, int stage, const ChunkArgs& a, int grid);
+// One RK stage over the tiles of family fam (see Family).
+hipError_t launch_stage(hipStream_t s, int dtype, int stage, int fam, const ChunkArgs& a, int grid);
 hipError_t launch_epilogue(hipStream_t s, const ChunkArgs& a);
 
 // Per-level set-up of one problem: Lax-Friedrichs bounds, time step and
@@ -32,7 +33,7 @@ hipError_t launch_mask(hipStream_t s, int dtype, const hjr_grid& g, const void* 
 // Fill n 64-bit words with value.
 hipError_t launch_fill_u64(hipStream_t s, uint64_t* p, int64_t n, uint64_t value);
 
-// Workgroups of the iteration kernel that fit on one compute unit.
-int stage_blocks_per_cu(int dtype);
+// Workgroups of a stage kernel that fit on one compute unit.
+int stage_blocks_per_cu(int dtype, int stage, int fam);
 
 }  // namespace hjr

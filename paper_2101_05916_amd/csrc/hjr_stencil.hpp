@@ -153,6 +153,12 @@ struct HamZ2D {
         const T vzh = c0 + (T)j1 * c1;  // (0.5/h0) vz
         return sum[0] * vzh + sum[1] * (sum[1] >= T(0) ? cpos : cneg);
     }
+    // plane tiles: no per-row table
+    __device__ __forceinline__ T row_coef(int) const { return T(0); }
+    __device__ __forceinline__ T eval(const T* sum, int j0, int j1, int j2, int j3, T) const
+    {
+        return (*this)(sum, j0, j1, j2, j3);
+    }
 };
 
 // x' = vx + d, vx' = g tan(theta), theta' = -d1 theta + omega,
@@ -178,14 +184,20 @@ struct HamX4D {
         n0s = hc[9];
         gts = (const T*)P.table;
     }
-    __device__ __forceinline__ T operator()(const T* sum, int j0, int j1, int j2, int j3) const
+    // table[j2], loaded by plane tiles together with the node's other loads
+    __device__ __forceinline__ T row_coef(int j2) const { return ld32(gts, (uint32_t)j2); }
+    __device__ __forceinline__ T eval(const T* sum, int j0, int j1, int j2, int j3, T g) const
     {
         const T cvx = c0 + (T)j1 * c1;                   // (0.5/h0) vx
         const T tw = A + (T)j3 * B - (T)j2 * C;          // (0.5/h2)(omega - d1 theta)
         const T t3 = D + (T)j2 * E;                      // (0.5/h3) d0 theta
         const T s0 = sum[0];
-        return s0 * (cvx + (s0 >= T(0) ? dl : dh)) + sum[1] * ld32(gts, (uint32_t)j2) + sum[2] * tw -
-               sum[3] * t3 + n0s * fabs(sum[3]);
+        return s0 * (cvx + (s0 >= T(0) ? dl : dh)) + sum[1] * g + sum[2] * tw - sum[3] * t3 +
+               n0s * fabs(sum[3]);
+    }
+    __device__ __forceinline__ T operator()(const T* sum, int j0, int j1, int j2, int j3) const
+    {
+        return eval(sum, j0, j1, j2, j3, row_coef(j2));
     }
 };
 
@@ -347,40 +359,52 @@ __device__ __forceinline__ void clamped_offsets(int j, int n, int s, int* o)
 
 // Tile t of a problem covers rows [r0, r1) of axis D-2 at a fixed index of
 // the outer axes (i0, i1 for D = 4); the host keeps (r1 - r0) * n_last <=
-// kPlaneNodesPT * kStageBlock.  The rows r0-2 .. r1+1 of the LDS block are
-// loaded in one batch; the outer-axis neighbours (and in stage 2, V and l)
-// of the nodes are loaded two nodes at a time.  The LDS block has columns -2 .. n_last+1 (stride RS);
-// out-of-range rows and columns hold the ghost extrapolations, so every
-// in-plane neighbour is a constant LDS offset.
+// kPlaneNodesPT * kStageBlock, (r1 - r0 + 4) * n_last <= kPlaneStagePT *
+// kStageBlock and (r1 - r0 + 4) * RS <= plane_elems(RS).  The rows r0-2 ..
+// r1+1 that exist are loaded in one batch into an LDS block with columns
+// -2 .. n_last+1 (stride RS); the missing rows and the columns past the ends
+// receive the ghost extrapolations, so every in-plane neighbour is a
+// constant LDS offset.  The outer-axis neighbours of a node (and in stage 2
+// its V and l) come straight from global memory, issued together per node.
+//
+// The staging and the node loop run without divergent branches: a lane past
+// the end loads a clamped index, and its LDS write goes to a spare slot
+// (plane_elems(RS) + lane) or its result is dropped; only uniform tests
+// skip whole groups of 64.
 template <typename T, int D, class Ham, int STAGE, int RS, int ORDER>
-__device__ uint64_t tile_plane(const ProbDesc& P, const ProbState& S, int64_t tile, T* lds)
+__device__ uint64_t tile_plane(const ProbDesc& P, const ProbState& S, uint32_t tile, T* lds)
 {
+    constexpr int kSpare = plane_elems(RS);
     const T* __restrict__ in = (const T*)(STAGE == 1 ? P.V : P.Vhat);
     const int ra = D - 2, ca = D - 1;  // row axis, column axis
     const int nr = P.n[ra], nc = P.n[ca];
-    const int chunk = (int)(tile % P.chunks);
-    const int outer = (int)(tile / P.chunks);
+    const uint32_t outer = P.chunks == 1 ? tile : fdiv(tile, P.div_chunks);
+    const int chunk = (int)(tile - outer * (uint32_t)P.chunks);
     int i0 = 0, i1 = 0;
     if (D == 4) {
-        i1 = outer % P.n[1];
-        i0 = outer / P.n[1];
+        i0 = (int)fdiv(outer, P.div[1]);
+        i1 = (int)outer - i0 * P.n[1];
     }
     const int r0 = chunk * P.rows;
     const int r1 = min(r0 + P.rows, nr);
-    const uint32_t plane0 = (uint32_t)outer * (uint32_t)(nr * nc);
+    const uint32_t plane0 = outer * (uint32_t)(nr * nc);
     const int lr0 = max(r0 - 2, 0), lr1 = min(r1 + 2, nr);
     const int nload = (lr1 - lr0) * nc;
     const uint32_t load0 = plane0 + (uint32_t)(lr0 * nc);  // the loaded rows are contiguous
+    const int lrow = lr0 - r0 + 2;                         // LDS row of the first loaded row
     const int cnt = (r1 - r0) * nc;
     const uint32_t node0 = plane0 + (uint32_t)(r0 * nc);
     const int tid = threadIdx.x;
 
-    // ---- every global load of the tile ----
+    // ---- every staging load of the tile ----
     T sv[kPlaneStagePT];
 #pragma unroll
     for (int k = 0; k < kPlaneStagePT; k++) {
-        const int e = tid + k * kStageBlock;
-        sv[k] = (e < nload) ? ld32(in, load0 + (uint32_t)e) : T(0);
+        sv[k] = T(0);
+        if (k * kStageBlock < nload) {
+            const uint32_t e = min((uint32_t)(tid + k * kStageBlock), (uint32_t)(nload - 1));
+            sv[k] = ld32(in, load0 + e);
+        }
     }
     int o0[4] = {0, 0, 0, 0}, o1[4] = {0, 0, 0, 0};
     if (D == 4) {
@@ -391,34 +415,21 @@ __device__ uint64_t tile_plane(const ProbDesc& P, const ProbState& S, int64_t ti
     // ---- LDS block: loaded rows, then ghost columns and ghost rows ----
 #pragma unroll
     for (int k = 0; k < kPlaneStagePT; k++) {
-        const int e = tid + k * kStageBlock;
-        if (e < nload) {
+        if (k * kStageBlock < nload) {
+            const int e = tid + k * kStageBlock;
             const int rr = (int)fdiv((uint32_t)e, P.div_last);
             const int cc = e - rr * nc;
-            lds[(lr0 - r0 + 2 + rr) * RS + cc + 2] = sv[k];
+            lds[e < nload ? (lrow + rr) * RS + cc + 2 : kSpare + tid] = sv[k];
         }
     }
     __syncthreads();
     const int nghc = (lr1 - lr0) * 4;
     for (int e = tid; e < nghc; e += kStageBlock) {
-        const int rr = e >> 2, k = e & 3;
-        T* row = lds + (lr0 + rr - r0 + 2) * RS + 2;  // row[c] is column c
-        T v;
-        int col;
-        if (k == 0) {
-            v = T(2) * row[0] - row[1];
-            col = -1;
-        } else if (k == 1) {
-            v = T(3) * row[0] - T(2) * row[1];
-            col = -2;
-        } else if (k == 2) {
-            v = T(2) * row[nc - 1] - row[nc - 2];
-            col = nc;
-        } else {
-            v = T(3) * row[nc - 1] - T(2) * row[nc - 2];
-            col = nc + 1;
-        }
-        row[col] = v;
+        // column -1 - s (left) or nc + s (right), s = 0, 1, of loaded row e/4
+        T* row = lds + (lrow + (e >> 2)) * RS + 2;
+        const bool right = (e & 2) != 0, far = (e & 1) != 0;
+        const T v0 = row[right ? nc - 1 : 0], v1 = row[right ? nc - 2 : 1];
+        row[right ? nc + (e & 1) : -1 - (e & 1)] = far ? T(3) * v0 - T(2) * v1 : T(2) * v0 - v1;
     }
     const bool glo = (r0 - 2 < 0), ghi = (r1 + 2 > nr);
     if (glo || ghi) {
@@ -454,27 +465,31 @@ __device__ uint64_t tile_plane(const ProbDesc& P, const ProbState& S, int64_t ti
     const bool edge0 = D == 4 && (i0 < 2 || i0 > P.n[0] - 3);
     const bool edge1 = D == 4 && (i1 < 2 || i1 > P.n[1] - 3);
     uint64_t rmax = 0;
-    // nodes two at a time: the global loads of a pair are issued together
-#pragma unroll HJR_NODE_UNROLL
+    constexpr int kUnroll = STAGE == 1 ? kNodeUnroll1 : kNodeUnroll2;
+#pragma unroll kUnroll
     for (int k = 0; k < kPlaneNodesPT; k++) {
-        const int e = tid + k * kStageBlock;
-        if (e < cnt) {
+        if (k * kStageBlock < cnt) {
+            // lanes past the end compute the last node again and drop it
+            const int e = min(tid + k * kStageBlock, cnt - 1);
+            const bool live = tid + k * kStageBlock < cnt;
             const uint32_t gi = node0 + (uint32_t)e;
+            const int rr = (int)fdiv((uint32_t)e, P.div_last);
+            const int cc = e - rr * nc;
             T w[8];
+            T rc = T(0);
             if (D == 4) {
 #pragma unroll
                 for (int qq = 0; qq < 4; qq++) {
                     w[qq] = ld32(in + o0[qq], gi);
                     w[4 + qq] = ld32(in + o1[qq], gi);
                 }
+                rc = ham.row_coef(r0 + rr);
             }
             T vo = T(0), lvv = T(0);
             if (STAGE == 2) {
                 vo = ld32((const T*)P.V, gi);
                 lvv = ld32((const T*)P.l, gi);
             }
-            const int rr = (int)fdiv((uint32_t)e, P.div_last);
-            const int cc = e - rr * nc;
             const T* q = lds + (rr + 2) * RS + cc + 2;
             const T c = q[0];
             T sum[4], dif;
@@ -494,18 +509,19 @@ __device__ uint64_t tile_plane(const ProbDesc& P, const ProbState& S, int64_t ti
                 if (edge1) ghost_fix<T>(i1, P.n[1], c, m2, m1, p1, p2);
                 eno_sd<T, ORDER>(m2, m1, c, p1, p2, sum[1], dif);
                 L += ah[1] * dif;
-                L += ham(sum, i0, i1, r0 + rr, cc);
+                L += ham.eval(sum, i0, i1, r0 + rr, cc, rc);
             } else {
-                L += ham(sum, r0 + rr, cc, 0, 0);
+                L += ham.eval(sum, r0 + rr, cc, 0, 0, rc);
             }
             if (STAGE == 1) {
-                st32((T*)P.Vhat, gi, c + dt * L);
+                if (live) st32((T*)P.Vhat, gi, c + dt * L);
             } else {
                 const T vt = c + dt * L;
                 const T avg = T(0.5) * (vo + vt);
                 const T vn = (lvv < avg) ? lvv : avg;
-                st32((T*)P.V, gi, vn);
-                if (in_band(vn, vo, P.band)) rmax = umax64(rmax, dbits(fabs((double)vn - (double)vo)));
+                if (live) st32((T*)P.V, gi, vn);
+                const uint64_t r = dbits(fabs((double)vn - (double)vo));
+                if (live && in_band(vn, vo, P.band)) rmax = umax64(rmax, r);
             }
         }
     }
@@ -513,32 +529,26 @@ __device__ uint64_t tile_plane(const ProbDesc& P, const ProbState& S, int64_t ti
     return rmax;
 }
 
-template <typename T, int STAGE>
-__device__ __forceinline__ uint64_t run_tile(const ProbDesc& P, const ProbState& S, int64_t tile,
+// One tile of a family (see Family): flat tiles dispatch on the model at run
+// time, plane families are fixed at compile time.
+template <typename T, int STAGE, int FAM>
+__device__ __forceinline__ uint64_t run_tile(const ProbDesc& P, const ProbState& S, uint32_t tile,
                                              T* lds)
 {
-    const bool o1 = P.order == 1;
-    switch (P.kind) {
-    case HJR_QUAD_Z2D:
-        if (P.path == kPathPlaneS)
-            return o1 ? tile_plane<T, 2, HamZ2D<T>, STAGE, kRowStrideS, 1>(P, S, tile, lds)
-                      : tile_plane<T, 2, HamZ2D<T>, STAGE, kRowStrideS, 2>(P, S, tile, lds);
-        if (P.path == kPathPlaneL)
-            return o1 ? tile_plane<T, 2, HamZ2D<T>, STAGE, kRowStrideL, 1>(P, S, tile, lds)
-                      : tile_plane<T, 2, HamZ2D<T>, STAGE, kRowStrideL, 2>(P, S, tile, lds);
-        return tile_flat<T, 2, HamZ2D<T>, STAGE>(P, S, tile);
-    case HJR_QUAD_X4D:
-        if (P.path == kPathPlaneS)
-            return o1 ? tile_plane<T, 4, HamX4D<T>, STAGE, kRowStrideS, 1>(P, S, tile, lds)
-                      : tile_plane<T, 4, HamX4D<T>, STAGE, kRowStrideS, 2>(P, S, tile, lds);
-        if (P.path == kPathPlaneL)
-            return o1 ? tile_plane<T, 4, HamX4D<T>, STAGE, kRowStrideL, 1>(P, S, tile, lds)
-                      : tile_plane<T, 4, HamX4D<T>, STAGE, kRowStrideL, 2>(P, S, tile, lds);
-        return tile_flat<T, 4, HamX4D<T>, STAGE>(P, S, tile);
-    case HJR_DI2X2:
-        return tile_flat<T, 4, HamDI2X2<T>, STAGE>(P, S, tile);
-    default:
-        return 0;
+    if constexpr (FAM == kFamFlat) {
+        switch (P.kind) {
+        case HJR_QUAD_Z2D: return tile_flat<T, 2, HamZ2D<T>, STAGE>(P, S, tile);
+        case HJR_QUAD_X4D: return tile_flat<T, 4, HamX4D<T>, STAGE>(P, S, tile);
+        case HJR_DI2X2: return tile_flat<T, 4, HamDI2X2<T>, STAGE>(P, S, tile);
+        default: return 0;
+        }
+    } else {
+        constexpr int RS = fam_rs(FAM);
+        constexpr int ORDER = fam_order(FAM);
+        if constexpr (fam_x4d(FAM))
+            return tile_plane<T, 4, HamX4D<T>, STAGE, RS, ORDER>(P, S, tile, lds);
+        else
+            return tile_plane<T, 2, HamZ2D<T>, STAGE, RS, ORDER>(P, S, tile, lds);
     }
 }
 
