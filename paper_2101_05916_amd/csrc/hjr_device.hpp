@@ -23,6 +23,18 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #ifndef HJR_NODE_UNROLL
 #define HJR_NODE_UNROLL 2            // nodes of a lane whose loads are issued together
 #endif
+#ifndef HJR_PLANE_QUAD1
+#define HJR_PLANE_QUAD1 0            // stage 1 plane tiles with 16-byte accesses (four nodes per lane)
+#endif
+#ifndef HJR_PLANE_QUAD2
+#define HJR_PLANE_QUAD2 1            // the same for stage 2
+#endif
+#ifndef HJR_HOIST_LOADS
+#define HJR_HOIST_LOADS 1            // issue a tile's first node loads before building its LDS block
+#endif
+#ifndef HJR_BLOCKS_PER_CU
+#define HJR_BLOCKS_PER_CU 24         // cap on stage workgroups per CU (6 single-wave groups per SIMD)
+#endif
 #ifndef HJR_WAVES_PER_EU
 #define HJR_WAVES_PER_EU 0           // occupancy hint for the stage kernels, 0 = none
 #endif
@@ -134,6 +146,14 @@ struct ProbDesc {
     int64_t ntiles;
 };
 
+// The stage kernels address the tables they only read (problem descriptors,
+// per-problem state, chunk header, control words and order list) in the
+// constant address space: those loads become scalar loads, and everything
+// derived from them is known to be uniform across a wave, so pointers and
+// buffer resources stay in SGPRs.
+#define HJR_CONST __attribute__((address_space(4)))
+typedef const HJR_CONST ProbDesc PDesc;
+
 // Family of a problem's tiles (its model, tile path and ENO order).
 inline int family_of(const ProbDesc& P)
 {
@@ -155,6 +175,8 @@ struct ProbState {
     uint64_t mask_count;
     double pad[1];
 };
+
+typedef const HJR_CONST ProbState PState;
 
 // Per-chunk header and per-problem control (written by the host each chunk).
 // The tiles of family f are [fam_tile[f], fam_tile[f+1]); its problems sit at

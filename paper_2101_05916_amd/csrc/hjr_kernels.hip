@@ -60,7 +60,7 @@ __device__ uint64_t block_max_u64(uint64_t v, uint64_t* red)
 
 // Order position owning tile t among positions [lo, hi) of a family: the
 // last one whose first tile is <= t (first tiles increase along the order).
-__device__ __forceinline__ int find_pos(const int64_t* tb, int lo, int hi, int64_t t)
+__device__ __forceinline__ int find_pos(const HJR_CONST int64_t* tb, int lo, int hi, int64_t t)
 {
     hi -= 1;
     while (lo < hi) {
@@ -75,11 +75,11 @@ __device__ __forceinline__ int find_pos(const int64_t* tb, int lo, int hi, int64
 
 __device__ __forceinline__ bool prob_active(const ChunkArgs& A, int p)
 {
-    if (A.slot >= A.ctl[p].limit) return false;
+    if (A.slot >= ((const HJR_CONST ProbCtl*)A.ctl)[p].limit) return false;
     uint64_t r = 0;
 #pragma unroll
     for (int s = 0; s < kResSubs; s++) r = umax64(r, A.res[res_index(p, A.slot, s, A.K)]);
-    return !(bitsd(r) < A.probs[p].tol);
+    return !(bitsd(r) < ((PDesc*)A.probs)[p].tol);
 }
 
 // Fold a workgroup's max |V' - V| into problem p's residual of this step.
@@ -100,11 +100,21 @@ __device__ __forceinline__ void flush_residual(const ChunkArgs& A, int p, uint64
     }
 }
 
-#if HJR_WAVES_PER_EU > 0
-#define HJR_STAGE_ATTR __attribute__((amdgpu_waves_per_eu(HJR_WAVES_PER_EU, 8)))
-#else
-#define HJR_STAGE_ATTR
+// Occupancy hint per stage (0 = none): asks the compiler to fit the stage
+// kernels in the registers of that many waves per SIMD.
+#ifndef HJR_WAVES_PER_EU1
+#define HJR_WAVES_PER_EU1 HJR_WAVES_PER_EU
 #endif
+#ifndef HJR_WAVES_PER_EU2
+#define HJR_WAVES_PER_EU2 HJR_WAVES_PER_EU
+#endif
+// The hint applies to the FP32 kernels only (FP64 tiles need the registers).
+#define HJR_STAGE_ATTR                                                                      \
+    __attribute__((amdgpu_waves_per_eu(                                                     \
+        sizeof(T) != 4 ? 1                                                                  \
+        : STAGE == 1   ? (HJR_WAVES_PER_EU1 > 0 ? HJR_WAVES_PER_EU1 : 1)                    \
+                       : (HJR_WAVES_PER_EU2 > 0 ? HJR_WAVES_PER_EU2 : 1),                   \
+        8)))
 
 // One RK stage over the tiles of family FAM.  The family's tiles are split
 // into eight contiguous ranges, one per XCD (workgroup b runs on XCD b mod
@@ -112,13 +122,18 @@ __device__ __forceinline__ void flush_residual(const ChunkArgs& A, int p, uint64
 template <typename T, int STAGE, int FAM>
 __global__ __launch_bounds__(kStageBlock) HJR_STAGE_ATTR void k_stage(ChunkArgs A)
 {
-    constexpr int kElems = FAM == kFamFlat ? 4 : plane_elems(fam_rs(FAM)) + kStageBlock;
+    constexpr int kElems = FAM == kFamFlat ? 4 : plane_elems(fam_rs(FAM)) + kStageBlock + 16;
     __shared__ uint64_t red[kStageBlock / 64];
     __shared__ __align__(16) char smem[kElems * sizeof(T)];
     T* lds = (T*)smem;
-    const int pb = A.hdr->fam_pos[FAM], pe = A.hdr->fam_pos[FAM + 1];
+    const HJR_CONST ChunkHdr* hdr = (const HJR_CONST ChunkHdr*)A.hdr;
+    const HJR_CONST int64_t* tb = (const HJR_CONST int64_t*)A.tb;
+    const HJR_CONST int32_t* ord = (const HJR_CONST int32_t*)A.ord;
+    PDesc* probs = (PDesc*)A.probs;
+    PState* states = (PState*)A.states;
+    const int pb = hdr->fam_pos[FAM], pe = hdr->fam_pos[FAM + 1];
     if (pb >= pe) return;
-    const int64_t t0 = A.hdr->fam_tile[FAM], t1 = A.hdr->fam_tile[FAM + 1];
+    const int64_t t0 = hdr->fam_tile[FAM], t1 = hdr->fam_tile[FAM + 1];
     const int64_t total = t1 - t0;
     const int G8 = (int)gridDim.x >> 3;
     const int xcd = (int)blockIdx.x & 7;
@@ -130,16 +145,16 @@ __global__ __launch_bounds__(kStageBlock) HJR_STAGE_ATTR void k_stage(ChunkArgs 
     uint64_t rmax = 0;
     for (int64_t t = beg + local; t < end; t += G8) {
         if (t >= hi || t < lo) {
-            const int pos = find_pos(A.tb, pb, pe, t);
+            const int pos = find_pos(tb, pb, pe, t);
             if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red);
-            cur = A.ord[pos];
-            lo = A.tb[pos];
-            hi = pos + 1 < pe ? A.tb[pos + 1] : t1;
+            cur = ord[pos];
+            lo = tb[pos];
+            hi = pos + 1 < pe ? tb[pos + 1] : t1;
             rmax = 0;
             active = prob_active(A, cur);
         }
         if (!active) continue;
-        rmax = umax64(rmax, run_tile<T, STAGE, FAM>(A.probs[cur], A.states[cur], (uint32_t)(t - lo), lds));
+        rmax = umax64(rmax, run_tile<T, STAGE, FAM>(probs[cur], states[cur], (uint32_t)(t - lo), lds));
     }
     if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red);
 }
@@ -571,6 +586,7 @@ int stage_blocks_per_cu(int dtype, int stage, int fam)
     int n = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kStageBlock, 0);
     if (e != hipSuccess || n < 1) n = 2;
+    if (HJR_BLOCKS_PER_CU > 0 && HJR_BLOCKS_PER_CU < n) n = HJR_BLOCKS_PER_CU;
     return n;
 }
 
