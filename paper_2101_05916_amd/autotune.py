@@ -96,6 +96,19 @@ def _wall_us(torch, hjr, spec, l, rows, chunk, steps, dtype):
     return 1e6 * (time.perf_counter() - t0) / max(st["iterations"], 1)
 
 
+def choose_rows(stage_us):
+    """Tile height with the least device time per step (ties: the taller)."""
+    return min(stage_us, key=lambda r: (stage_us[r], -int(r)))
+
+
+def choose_chunk(wall_us):
+    """The shortest chunk within 2% of the least wall time per step: a solve
+    overshoots its stop step by up to a chunk of (skipped) launches, so a
+    shorter chunk wins when the per-step rates tie."""
+    best = min(wall_us.values())
+    return min(int(k) for k, v in wall_us.items() if v <= 1.02 * best)
+
+
 def tune(problems, dtypes=("f32",), steps=64, log=print):
     """problems: workload Problem objects (model, grid, bounds).  The steps
     run from l with max_iter set, so the measured solves never converge."""
@@ -109,10 +122,10 @@ def tune(problems, dtypes=("f32",), steps=64, log=print):
             dtype = torch.float32 if dts == "f32" else torch.float64
             l = torch.tensor(P.l, dtype=dtype, device="cuda")
             rows = {r: _stage_us(hjr, spec, l, r, steps, dtype) for r in row_candidates(P.n)}
-            best_r = min(rows, key=lambda r: (rows[r], -r))
+            best_r = choose_rows(rows)
             walls = {k: _wall_us(torch, hjr, spec, l, best_r, k, max(steps, 4 * k), dtype)
                      for k in CHUNK_CANDIDATES}
-            best_k = min(walls, key=lambda k: (walls[k] * 1.02 ** np.log2(k), k))
+            best_k = choose_chunk(walls)
             e = {"tile_rows": int(best_r), "chunk": int(best_k),
                  "stage_us": {str(r): round(v, 2) for r, v in rows.items()},
                  "step_wall_us": {str(k): round(v, 2) for k, v in walls.items()}}
@@ -141,7 +154,7 @@ def main():
                    log=lambda s: print(s, flush=True))
     doc = {"device": dev.name, "gcn_arch": getattr(dev, "gcnArchName", ""),
            "note": "tile_rows: least device time of the two stage launches per step; "
-                   "chunk: least wall time per step (2% penalty per doubling)",
+                   "chunk: shortest within 2% of the least wall time per step",
            "entries": entries}
     with open(a.out, "w") as fh:
         json.dump(doc, fh, indent=1, sort_keys=True)

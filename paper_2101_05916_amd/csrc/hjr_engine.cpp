@@ -129,6 +129,11 @@ Engine::Engine(const EngineCfg& cfg) : cfg_(cfg)
 Engine::~Engine()
 {
     if (stream_) (void)hipStreamSynchronize(stream_);
+    for (int f = 0; f < kNumFam; f++) {
+        if (side_[f]) (void)hipStreamDestroy(side_[f]);
+        if (join_ev_[f]) (void)hipEventDestroy(join_ev_[f]);
+    }
+    if (fork_ev_) (void)hipEventDestroy(fork_ev_);
     for (auto& f : flights_)
         if (f.ev) (void)hipEventDestroy(f.ev);
     for (int p = 0; p < 2; p++) {
@@ -214,6 +219,13 @@ hjr_status Engine::init(hipStream_t stream, void* arena)
             prof_ev_[q].resize(4 * (size_t)K);
             for (auto& e : prof_ev_[q]) HJR_TRY(hipEventCreate(&e));
         }
+    if (use_graph_) {
+        HJR_TRY(hipEventCreateWithFlags(&fork_ev_, hipEventDisableTiming));
+        for (int f = 0; f < kNumFam; f++) {
+            HJR_TRY(hipStreamCreateWithFlags(&side_[f], hipStreamNonBlocking));
+            HJR_TRY(hipEventCreateWithFlags(&join_ev_[f], hipEventDisableTiming));
+        }
+    }
     slots_.assign(cap, nullptr);
     table_dirty_ = true;
     return HJR_OK;
@@ -447,15 +459,39 @@ ChunkArgs Engine::args(int par, int slot) const
     return a;
 }
 
-hjr_status Engine::enqueue_chunk_body(int par, bool timed)
+// One RK stage: a launch per family present.  With `fork` (graph capture)
+// the second and later families go to side streams that fork from and join
+// back into the engine stream, so the captured graph runs them as parallel
+// branches; the first family stays on the engine stream.
+hjr_status Engine::enqueue_stage(int stage, const ChunkArgs& a, bool fork)
+{
+    const int n = (int)launches_.size();
+    if (!fork || n < 2) {
+        for (const Launch& l : launches_)
+            HJR_TRY(launch_stage(stream_, cfg_.dtype, stage, l.fam, a, l.grid[stage - 1]));
+        return HJR_OK;
+    }
+    HJR_TRY(hipEventRecord(fork_ev_, stream_));
+    for (int i = 1; i < n; i++) {
+        const Launch& l = launches_[i];
+        HJR_TRY(hipStreamWaitEvent(side_[l.fam], fork_ev_, 0));
+        HJR_TRY(launch_stage(side_[l.fam], cfg_.dtype, stage, l.fam, a, l.grid[stage - 1]));
+        HJR_TRY(hipEventRecord(join_ev_[l.fam], side_[l.fam]));
+    }
+    HJR_TRY(launch_stage(stream_, cfg_.dtype, stage, launches_[0].fam, a, launches_[0].grid[stage - 1]));
+    for (int i = 1; i < n; i++) HJR_TRY(hipStreamWaitEvent(stream_, join_ev_[launches_[i].fam], 0));
+    return HJR_OK;
+}
+
+hjr_status Engine::enqueue_chunk_body(int par, bool timed, bool fork)
 {
     HJR_TRY(launch_prologue(stream_, args(par, 0)));
     for (int s = 0; s < cfg_.K; s++) {
         const ChunkArgs a = args(par, s);
         for (int stage = 1; stage <= 2; stage++) {
             if (timed) HJR_TRY(hipEventRecord(prof_ev_[par][4 * s + 2 * (stage - 1)], stream_));
-            for (const Launch& l : launches_)
-                HJR_TRY(launch_stage(stream_, cfg_.dtype, stage, l.fam, a, l.grid[stage - 1]));
+            hjr_status st = enqueue_stage(stage, a, fork);
+            if (st != HJR_OK) return st;
             if (timed) HJR_TRY(hipEventRecord(prof_ev_[par][4 * s + 2 * (stage - 1) + 1], stream_));
         }
     }
@@ -467,7 +503,7 @@ hjr_status Engine::build_graph(int par, hipGraphExec_t* out)
 {
     hipGraph_t g = nullptr;
     HJR_TRY(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-    hjr_status st = enqueue_chunk_body(par, false);
+    hjr_status st = enqueue_chunk_body(par, false, true);
     hipError_t e = hipStreamEndCapture(stream_, &g);
     if (st != HJR_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -545,7 +581,7 @@ hjr_status Engine::step()
         // launch: events between kernels cost throughput, so the sample keeps
         // the rest of the run undisturbed
         f.timed = profile_ && (chunk_ % kProfileEvery == 0);
-        hjr_status st = enqueue_chunk_body(par, f.timed);
+        hjr_status st = enqueue_chunk_body(par, f.timed, false);
         if (st != HJR_OK) return st;
     }
     HJR_TRY(hipMemcpyAsync(h_compact_[par], d_compact_[par], sizeof(double) * (size_t)cap * K,

@@ -130,7 +130,8 @@ private:
 
     hjr_status setup_level(Job* j);
     hjr_status upload_table();
-    hjr_status enqueue_chunk_body(int par, bool timed);
+    hjr_status enqueue_chunk_body(int par, bool timed, bool fork);
+    hjr_status enqueue_stage(int stage, const ChunkArgs& a, bool fork);
     hjr_status build_graph(int par, hipGraphExec_t* out);
     hjr_status process(Flight& f);
     void finish_level(Job* j, int status, int64_t iters, double residual);
@@ -149,6 +150,12 @@ private:
 
     EngineCfg cfg_;
     hipStream_t stream_ = nullptr;
+    // side streams and events that let the launches of different families
+    // in one stage run concurrently inside a captured graph (fork on
+    // fork_ev_, join on join_ev_[f])
+    hipStream_t side_[kNumFam] = {};
+    hipEvent_t fork_ev_ = nullptr;
+    hipEvent_t join_ev_[kNumFam] = {};
     int fam_grid_[2][kNumFam] = {};  // workgroup cap per stage and family (occupancy x CUs)
     bool own_arena_ = false;
     void* arena_ = nullptr;

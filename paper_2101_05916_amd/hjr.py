@@ -275,13 +275,25 @@ def workspace_bytes(spec: Spec, opts: Opts) -> int:
     return out.value
 
 
+def tuned(kind, dtype, n):
+    """Autotuned {"tile_rows", "chunk"} for a grid shape (autotune.py), or {}."""
+    from . import autotune
+    return autotune.lookup(kind, _dtype_code(dtype), n) or {}
+
+
 def solve(spec: Spec, l, V0=None, V_out=None, *, dtype=None, order=2, cfl=0.8,
-          max_iter=100000, chunk=0, flags=0, workspace=True, check=True, tile_rows=0):
+          max_iter=100000, chunk=None, flags=0, workspace=True, check=True, tile_rows=None):
     """One safe-set solve.  l, V0, V_out: device tensors of spec.size elements.
-    Returns (V_out, stats dict).  Raises HjrError on failure; a solve that
-    hits max_iter returns with stats['status'] == NOT_CONVERGED."""
+    chunk / tile_rows None take the autotuned values for this shape (library
+    defaults if it was not tuned).  Returns (V_out, stats dict).  Raises
+    HjrError on failure; a solve that hits max_iter returns with
+    stats['status'] == NOT_CONVERGED."""
     torch = _torch()
     dtype = dtype or l.dtype
+    if chunk is None or tile_rows is None:
+        t = tuned(spec.kind, dtype, spec.n)
+        chunk = t.get("chunk", 0) if chunk is None else chunk
+        tile_rows = t.get("tile_rows", 0) if tile_rows is None else tile_rows
     N = spec.size
     _check_tensor(l, N, dtype, "l")
     if V0 is not None:
@@ -343,9 +355,11 @@ def solve_levels(spec: Spec, grids_n, ls, V0=None, *, dtype=None, order=2, cfl=0
     return Vs, mk, (list(counts) if masks else None), out
 
 
-def make_problem(spec: Spec, l, V_out, V0=None, levels=None, tile_rows=None) -> Problem:
+def make_problem(spec: Spec, l, V_out, V0=None, levels=None, tile_rows=None,
+                 dtype=None) -> Problem:
     """levels: optional list of (n, l_k, V_k) for a coarse-to-fine job; else
-    one level with (spec.n, l, V_out)."""
+    one level with (spec.n, l, V_out).  tile_rows None takes the autotuned
+    height of every level's shape (dtype: that of the level arrays)."""
     p = Problem()
     p.dyn = make_dyn(spec.kind, spec.params)
     if levels is None:
@@ -361,17 +375,27 @@ def make_problem(spec: Spec, l, V_out, V0=None, levels=None, tile_rows=None) -> 
     p.d[1] = dd[1]
     p.tol = spec.tol
     p.band = spec.band
-    for k, r in enumerate(tile_rows or []):
+    if tile_rows is None:
+        tile_rows = [tuned(spec.kind, dtype or lk.dtype, n).get("tile_rows", 0)
+                     for n, lk, _ in levels]
+    for k, r in enumerate(tile_rows):
         p.tile_rows[k] = int(r)
     return p
 
 
-def solve_batch(problems, *, dtype=None, order=2, cfl=0.8, max_iter=100000, chunk=0,
+def solve_batch(problems, *, dtype=None, order=2, cfl=0.8, max_iter=100000, chunk=None,
                 flags=0, device=None):
-    """problems: list of Problem structs (make_problem).  Returns (return
+    """problems: list of Problem structs (make_problem).  chunk None takes the
+    autotuned chunk of the largest grid in the batch.  Returns (return
     status, list of stats dicts)."""
     torch = _torch()
     n = len(problems)
+    if chunk is None:
+        big = max(problems, key=lambda p: max(int(np.prod([p.grids[k].n[i] for i in range(p.grids[k].ndim)]))
+                                             for k in range(p.nlev)))
+        g = big.grids[big.nlev - 1]
+        chunk = tuned(big.dyn.kind, dtype or torch.float32,
+                      [g.n[i] for i in range(g.ndim)]).get("chunk", 0)
     arr = (Problem * n)(*problems)
     o = make_opts(dtype or torch.float32, order, cfl, max_iter, chunk, flags)
     nb = C.c_size_t(0)
