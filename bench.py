@@ -370,15 +370,16 @@ def mode_copy(args, torch, hjr, W):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_stage_decomposed_quad10d.json")
-KERNEL_SOURCES = ["hjr_stencil.hpp", "hjr_kernels.hip", "hjr_device.hpp", "hjr_engine.cpp"]
+KERNEL_SOURCES = ["csrc/hjr_stencil.hpp", "csrc/hjr_kernels.hip", "csrc/hjr_device.hpp", "tuned.json"]
 
 
 def kernel_hash():
-    """Hash of the sources that define the stage kernels and their tiles."""
+    """Hash of what defines the stage kernels' memory traffic: their sources
+    (tile code, launch caps) and the tuned tile heights."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2101_05916_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(ROOT, "paper_2101_05916_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 

@@ -148,8 +148,11 @@ typedef struct hjr_stats {
     int64_t cell_updates;   /* sum over levels of (nodes x steps) */
     double device_ms;       /* device time from the first enqueue to completion */
     double kernel_ms[2];    /* with HJR_FLAG_PROFILE: summed device time of the
-                               timed RK stage-1 and stage-2 launches */
-    int64_t kernel_launches[2]; /* with HJR_FLAG_PROFILE: number of timed launches */
+                               timed RK stage-1 and stage-2 launches (one chunk
+                               in eight; a stage's launches of all tile families
+                               count as one; steps past every problem's stop
+                               step are left out) */
+    int64_t kernel_launches[2]; /* with HJR_FLAG_PROFILE: number of timed stages */
     int64_t kernel_cell_updates; /* with HJR_FLAG_PROFILE: cell-updates those timed
                                     launches performed */
 } hjr_stats;

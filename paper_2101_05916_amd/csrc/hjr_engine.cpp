@@ -553,6 +553,15 @@ hjr_status Engine::step()
             j->fresh = false;
         }
     }
+    bool any = false;
+    for (int s = 0; s < cap; s++) any = any || f.limit[s] > 0;
+    if (!any && !flights_.empty()) {
+        // nothing can advance until the chunk in flight is read back (its
+        // problems hit max_iter or start a new level there)
+        Flight g = std::move(flights_.front());
+        flights_.erase(flights_.begin());
+        return process(g);
+    }
     HJR_TRY(hipMemcpyAsync(d_hdr_[par], h_ctl_[par], ctl_bytes_, hipMemcpyHostToDevice, stream_));
     // one launch per family present, with no more workgroups than it has
     // tiles (a multiple of 8, so that every XCD gets its share)
@@ -622,8 +631,23 @@ hjr_status Engine::process(Flight& f)
     const int par = (int)(f.chunk & 1);
     const double* r = h_compact_[par];
     const int K = cfg_.K;
-    if (f.timed)
-        for (int s = 0; s < K; s++)
+    std::vector<int> hits(cfg_.cap, -1);
+    int steps_live = 0;  // steps of this chunk in which some problem did work
+    for (int s = 0; s < cfg_.cap; s++) {
+        Job* j = f.job[s];
+        const int lim = f.limit[s];
+        if (!j || j->done || lim == 0) continue;
+        if (j->slot != s || j->level_start_chunk > f.chunk) continue;  // stale results
+        const double* rs = r + (int64_t)s * K;
+        for (int k = 0; k < lim; k++)
+            if (rs[k] < j->tol) {
+                hits[s] = k;
+                break;
+            }
+        steps_live = std::max(steps_live, hits[s] >= 0 ? hits[s] + 1 : lim);
+    }
+    if (f.timed)  // the skipped look-ahead steps past every stop are not counted
+        for (int s = 0; s < steps_live; s++)
             for (int st = 0; st < 2; st++) {
                 float ms = 0.f;
                 HJR_TRY(hipEventElapsedTime(&ms, prof_ev_[par][4 * s + 2 * st],
@@ -637,12 +661,7 @@ hjr_status Engine::process(Flight& f)
         if (!j || j->done || lim == 0) continue;
         if (j->slot != s || j->level_start_chunk > f.chunk) continue;  // stale results
         const double* rs = r + (int64_t)s * K;
-        int hit = -1;
-        for (int k = 0; k < lim; k++)
-            if (rs[k] < j->tol) {
-                hit = k;
-                break;
-            }
+        const int hit = hits[s];
         if (f.timed) prof_cells_ += grid_size(j->lev[j->cur].grid) * (hit >= 0 ? hit + 1 : lim);
         if (hit >= 0) {
             finish_level(j, HJR_OK, f.sched[s] + hit + 1, rs[hit]);
