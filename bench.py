@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "warm", "copy"])
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "warm", "copy", "precision"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk", type=int, default=None, help="RK2 steps per chunk (default: autotuned)")
@@ -354,6 +354,42 @@ def mode_warm(args, torch, hjr, W):
 
 
 # ---------------------------------------------------------------------------
+# precision: the FP32 path against the FP64 path (which the parity tests pin
+# to the FP64 oracle) on the configurations' grids
+# ---------------------------------------------------------------------------
+
+def mode_precision(args, torch, hjr, W):
+    band = W.BAND_4D_UPDATE
+    cases = [
+        ("config 1: 2-D 101^2, dbar 0.5, cold", [W.quad_z2d(101, 0.5)]),
+        ("config 2: x-subsystem 21^4 -> 41^4, dbar 0.5", [W.quad_x4d(21, 0.5), W.quad_x4d(41, 0.5)]),
+        ("config 2: z-subsystem 51^2 -> 101^2, dbar 0.5", [W.quad_z2d(51, 0.5), W.quad_z2d(101, 0.5)]),
+        ("config 3: x-subsystem 21^4 -> 41^4 -> 61^4, dbar 0.8, band 0.5",
+         [W.quad_x4d(n, 0.8, band=band) for n in (21, 41, 61)]),
+        ("config 4 class: x-subsystem 31^4 cold, dbar 0.6, band 0.5", [W.quad_x4d(31, 0.6, band=band)]),
+    ]
+    out = {"metric": "FP32 path vs FP64 path", "mode": "precision", "cases": []}
+    for name, Ps in cases:
+        res = {}
+        for dt in (torch.float32, torch.float64):
+            ls = [torch.tensor(P.l, dtype=dt, device="cuda") for P in Ps]
+            Vs, _, _, st = hjr.solve_levels(hjr.Spec.of(Ps[-1]), [P.n for P in Ps], ls, dtype=dt)
+            res[dt] = (Vs[-1].double().cpu().numpy(), st)
+        a, sa = res[torch.float32]
+        b, sb = res[torch.float64]
+        e = {"case": name, "iterations_f32": sa["level_iterations"][: len(Ps)],
+             "iterations_f64": sb["level_iterations"][: len(Ps)],
+             "status": [sa["status"], sb["status"]],
+             "max_abs_diff": float(np.max(np.abs(a - b))),
+             # over the nodes that decide the safe set (|V| < 0.5 in the FP64 result)
+             "max_abs_diff_band_0.5": float(np.max(np.abs(a - b)[np.abs(b) < 0.5])),
+             "zero_level_disagreement": float(np.mean((a >= 0) != (b >= 0)))}
+        out["cases"].append(e)
+        progress(f"{name}: {e}")
+    return out
+
+
+# ---------------------------------------------------------------------------
 # copy mode: a plain device copy of known size, to calibrate the HBM byte
 # counters (FETCH_SIZE / WRITE_SIZE) that rocprofv3 reports for the kernels
 # ---------------------------------------------------------------------------
@@ -411,7 +447,7 @@ def main():
         sys.exit(2)
     hjr.lib()
     fn = {"step": mode_step, "batch": mode_batch, "serve": mode_serve, "warm": mode_warm,
-          "copy": mode_copy}[args.mode]
+          "copy": mode_copy, "precision": mode_precision}[args.mode]
     out = fn(args, torch, hjr, W)
     print(json.dumps(out), flush=True)
 

@@ -425,6 +425,39 @@ __device__ __forceinline__ void clamped_offsets(int j, int n, int s, int* o)
     o[3] = j <= n - 3 ? 2 * s : (j <= n - 2 ? s : 0);
 }
 
+// Stage the loaded rows of a plane tile (nlr rows of nc nodes from element
+// load0) into LDS rows lrow.. of stride RS, columns at +2: element e = lane +
+// 64 k of the loaded rows goes to LDS row e / nc, column e mod nc (one
+// multiply-high division).  All loads are issued before the first LDS write;
+// lanes past the end load a clamped element and write it to their spare slot.
+// (Staging column by column instead -- lane c owns column c, no division --
+// executed more vector instructions in total and ran slower.)
+template <typename T, int RS>
+__device__ __forceinline__ void stage_flat(const T* in, uint32_t load0, int nc, int nlr, int lrow,
+                                           T* lds, int tid, const HJR_CONST FastDiv& div_nc)
+{
+    constexpr int kSpare = plane_elems(RS);
+    const int nload = nlr * nc;
+    T sv[kPlaneStagePT];
+#pragma unroll
+    for (int k = 0; k < kPlaneStagePT; k++) {
+        sv[k] = T(0);
+        if (k * kStageBlock < nload) {
+            const uint32_t e = min((uint32_t)(tid + k * kStageBlock), (uint32_t)(nload - 1));
+            sv[k] = gld1<T>(in, (load0 + e) * (uint32_t)sizeof(T));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPlaneStagePT; k++) {
+        if (k * kStageBlock < nload) {
+            const int e = tid + k * kStageBlock;
+            const int rr = (int)fdiv((uint32_t)e, div_nc);
+            const int cc = e - rr * nc;
+            lds[e < nload ? (lrow + rr) * RS + cc + 2 : kSpare + tid] = sv[k];
+        }
+    }
+}
+
 // Tile t of a problem covers rows [r0, r1) of axis D-2 at a fixed index of
 // the outer axes (i0, i1 for D = 4); the host keeps (r1 - r0) * n_last <=
 // kPlaneNodesPT * kStageBlock, (r1 - r0 + 4) * n_last <= kPlaneStagePT *
@@ -442,7 +475,6 @@ __device__ __forceinline__ void clamped_offsets(int j, int n, int s, int* o)
 template <typename T, int D, class Ham, int STAGE, int RS, int ORDER>
 __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
 {
-    constexpr int kSpare = plane_elems(RS);
     const T* __restrict__ in = (const T*)(STAGE == 1 ? P.V : P.Vhat);
     const int ra = D - 2, ca = D - 1;  // row axis, column axis
     const int nr = P.n[ra], nc = P.n[ca];
@@ -457,7 +489,6 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
     const int r1 = min(r0 + P.rows, nr);
     const uint32_t plane0 = outer * (uint32_t)(nr * nc);
     const int lr0 = max(r0 - 2, 0), lr1 = min(r1 + 2, nr);
-    const int nload = (lr1 - lr0) * nc;
     const uint32_t load0 = plane0 + (uint32_t)(lr0 * nc);  // the loaded rows are contiguous
     const int lrow = lr0 - r0 + 2;                         // LDS row of the first loaded row
     const int cnt = (r1 - r0) * nc;
@@ -465,16 +496,6 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
     const int tid = threadIdx.x;
     constexpr uint32_t B = sizeof(T);
 
-    // ---- every staging load of the tile ----
-    T sv[kPlaneStagePT];
-#pragma unroll
-    for (int k = 0; k < kPlaneStagePT; k++) {
-        sv[k] = T(0);
-        if (k * kStageBlock < nload) {
-            const uint32_t e = min((uint32_t)(tid + k * kStageBlock), (uint32_t)(nload - 1));
-            sv[k] = gld1<T>(in, (load0 + e) * B);
-        }
-    }
     // outer-axis neighbours: one uniform base pointer per neighbour, shared
     // by every node of the tile, and the node's byte offset in a VGPR
     int o0[4] = {0, 0, 0, 0}, o1[4] = {0, 0, 0, 0};
@@ -490,15 +511,7 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
     }
 
     // ---- LDS block: loaded rows, then ghost columns and ghost rows ----
-#pragma unroll
-    for (int k = 0; k < kPlaneStagePT; k++) {
-        if (k * kStageBlock < nload) {
-            const int e = tid + k * kStageBlock;
-            const int rr = (int)fdiv((uint32_t)e, P.div_last);
-            const int cc = e - rr * nc;
-            lds[e < nload ? (lrow + rr) * RS + cc + 2 : kSpare + tid] = sv[k];
-        }
-    }
+    stage_flat<T, RS>(in, load0, nc, lr1 - lr0, lrow, lds, tid, P.div_last);
     __syncthreads();
     const int nghc = (lr1 - lr0) * 4;
     for (int e = tid; e < nghc; e += kStageBlock) {
@@ -618,7 +631,6 @@ __device__ uint64_t tile_plane_q(PDesc& P, PState& S, uint32_t tile, T* lds)
 {
     constexpr int kSpare = plane_elems(RS);
     constexpr int kTab = kSpare + kStageBlock;  // LDS offset of the row table
-    constexpr int kStageQ = kPlaneStagePT / 4;  // staging quads per lane
     constexpr int kNodeQ = kPlaneNodesPT / 4;   // node quads per lane
     const T* __restrict__ in = (const T*)(STAGE == 1 ? P.V : P.Vhat);
     const int ra = D - 2, ca = D - 1;  // row axis, column axis
@@ -634,7 +646,6 @@ __device__ uint64_t tile_plane_q(PDesc& P, PState& S, uint32_t tile, T* lds)
     const int r1 = min(r0 + P.rows, nr);
     const uint32_t plane0 = outer * (uint32_t)(nr * nc);
     const int lr0 = max(r0 - 2, 0), lr1 = min(r1 + 2, nr);
-    const int nload = (lr1 - lr0) * nc;
     const uint32_t load0 = plane0 + (uint32_t)(lr0 * nc);  // the loaded rows are contiguous
     const int lrow = lr0 - r0 + 2;                         // LDS row of the first loaded row
     const int cnt = (r1 - r0) * nc;
@@ -644,21 +655,6 @@ __device__ uint64_t tile_plane_q(PDesc& P, PState& S, uint32_t tile, T* lds)
     Ham ham;
     ham.init(P);
 
-    // ---- staging loads ----
-    T sv[kStageQ][4];
-#pragma unroll
-    for (int k = 0; k < kStageQ; k++) {
-        if (4 * k * kStageBlock < nload) {
-            const int s0 = 4 * (tid + k * kStageBlock);
-            if (s0 + 3 < nload) {
-                gld4<T>(sv[k], in, (load0 + (uint32_t)s0) * B);
-            } else if (s0 < nload) {
-#pragma unroll
-                for (int j = 0; j < 4; j++)
-                    sv[k][j] = gld1<T>(in, (load0 + (uint32_t)min(s0 + j, nload - 1)) * B);
-            }
-        }
-    }
     if (D == 4 && tid < r1 - r0) lds[kTab + tid] = ham.row_coef(r0 + tid);
     // outer-axis neighbours: one uniform base pointer per neighbour, shared
     // by every node of the tile, and the node's byte offset in a VGPR
@@ -710,18 +706,7 @@ __device__ uint64_t tile_plane_q(PDesc& P, PState& S, uint32_t tile, T* lds)
     if (HJR_HOIST_LOADS) load_group(0, w0, vo0, lv0);
 
     // ---- LDS block: loaded rows, then ghost columns and ghost rows ----
-#pragma unroll
-    for (int k = 0; k < kStageQ; k++) {
-        if (4 * k * kStageBlock < nload) {
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int e = 4 * (tid + k * kStageBlock) + j;
-                const int rr = (int)fdiv((uint32_t)e, P.div_last);
-                const int cc = e - rr * nc;
-                lds[e < nload ? (lrow + rr) * RS + cc + 2 : kSpare + tid] = sv[k][j];
-            }
-        }
-    }
+    stage_flat<T, RS>(in, load0, nc, lr1 - lr0, lrow, lds, tid, P.div_last);
     __syncthreads();
     const int nghc = (lr1 - lr0) * 4;
     for (int e = tid; e < nghc; e += kStageBlock) {

@@ -164,6 +164,31 @@ def test_first_order_matches_oracle():
     assert np.max(np.abs(V - ref["V"])) <= FP64_TOL
 
 
+# ---------------------------------------------------------------- every tile family
+
+# (shape, order): the plane-tile families the configurations above leave out
+# -- 4-D planes wider than 68 nodes (row stride 208), and first-order 4-D and
+# wide 2-D planes -- each with tiles whose node count is not a multiple of 4
+# (the FP32 16-byte stage-2 tile's partial quad)
+FAMILY_CASES = [("x4d", (5, 6, 7, 75), 2), ("x4d", (5, 6, 7, 75), 1), ("x4d", (9, 11, 13, 15), 1),
+                ("z2d", (83, 97), 1), ("x4d", (4, 5, 11, 69), 2)]
+
+
+@pytest.mark.parametrize("case", FAMILY_CASES, ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[1]))}-o{c[2]}")
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_tile_families_match_oracle(case, dt):
+    kind, shape, order = case
+    P = W.quad_x4d(shape, 0.6) if kind == "x4d" else W.quad_z2d(shape, 0.6)
+    steps = 30
+    ref = oracle_solve(P, order=order, max_iter=steps)
+    V, st = device_solve(P, torch.float64 if dt == "f64" else torch.float32, order=order,
+                         max_iter=steps)
+    err = float(np.max(np.abs(V - ref["V"])))
+    print(f"{kind} {shape} order {order} {dt}: {steps} steps, max|dV| {err:.3e}")
+    assert st["iterations"] == ref["iterations"] == steps
+    assert err <= (FP64_TOL if dt == "f64" else 1e-4)
+
+
 # ---------------------------------------------------------------- warm start
 
 def test_warm_start_fp64_matches_oracle():
