@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "warm", "copy", "precision"])
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "warm", "copy", "precision", "kernels"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk", type=int, default=None, help="RK2 steps per chunk (default: autotuned)")
@@ -390,6 +390,25 @@ def mode_precision(args, torch, hjr, W):
 
 
 # ---------------------------------------------------------------------------
+# kernels: the dominant kernel's workload alone, for hardware-counter runs
+# ---------------------------------------------------------------------------
+
+def mode_kernels(args, torch, hjr, W):
+    """64 RK2 steps of the step's two 4-D subsystems on 41^4, batched, launched
+    kernel by kernel (no graph), so that a counter collector sees plain
+    stage launches of the dominant family."""
+    Ps = [W.quad_x4d(41, 0.5, "x"), W.quad_x4d(41, 0.5, "y")]
+    ls = [torch.tensor(P.l, dtype=torch.float32, device="cuda") for P in Ps]
+    Vs = [torch.empty_like(l) for l in ls]
+    probs = [hjr.make_problem(hjr.Spec.of(P), l, V) for P, l, V in zip(Ps, ls, Vs)]
+    _, st = hjr.solve_batch(probs, max_iter=64, chunk=16,
+                            flags=hjr.FLAG_NO_GRAPH | hjr.FLAG_NO_PIPELINE)
+    torch.cuda.synchronize()
+    return {"mode": "kernels", "workload": "x, y 41^4 FP32 batched, 64 RK2 steps",
+            "iterations": st[0]["iterations"]}
+
+
+# ---------------------------------------------------------------------------
 # copy mode: a plain device copy of known size, to calibrate the HBM byte
 # counters (FETCH_SIZE / WRITE_SIZE) that rocprofv3 reports for the kernels
 # ---------------------------------------------------------------------------
@@ -447,7 +466,7 @@ def main():
         sys.exit(2)
     hjr.lib()
     fn = {"step": mode_step, "batch": mode_batch, "serve": mode_serve, "warm": mode_warm,
-          "copy": mode_copy, "precision": mode_precision}[args.mode]
+          "copy": mode_copy, "precision": mode_precision, "kernels": mode_kernels}[args.mode]
     out = fn(args, torch, hjr, W)
     print(json.dumps(out), flush=True)
 
