@@ -222,11 +222,12 @@ def test_launch_modes_bit_identical(flags, chunk):
 
 # ---------------------------------------------------------------- full-size sampled
 
-@pytest.mark.parametrize("n", [41, 61])
+@pytest.mark.parametrize("n", [41, 61, 81])
 def test_x4d_fullsize_sampled_step(n):
-    """At the benchmark sizes: run k device steps, then one more, and check
-    the last step at sampled nodes (all corners and edges included) against
-    the oracle's single-node step from the device's own V_k."""
+    """At the benchmark sizes (and 81^4, whose 81-node planes take the wide
+    LDS tiles): run k device steps, then one more, and check the last step
+    at sampled nodes (all corners and edges included) against the oracle's
+    single-node step from the device's own V_k."""
     import torch as T
     from paper_2101_05916_amd import hjr
     P = W.quad_x4d(n, 0.5)
