@@ -135,6 +135,25 @@ static void box_vertex(int m, const double* lo, const double* hi, int v,
     for (int i = 0; i < m; i++) out[i] = ((v >> i) & 1) ? hi[i] : lo[i];
 }
 
+/* Disturbance box of node idx (Sec. II-A: the disturbance set D(x) may
+ * depend on the state).  With a per-node field, channel c is bounded by
+ * dfield[(2c) N + idx] below and dfield[(2c + 1) N + idx] above; without
+ * one, by the constant box dlo[c], dhi[c]. */
+static void node_dbox(int md, const double* dlo, const double* dhi,
+                      const double* dfield, int64_t N, int64_t idx,
+                      double* lo, double* hi)
+{
+    for (int c = 0; c < md; c++) {
+        if (dfield) {
+            lo[c] = dfield[(int64_t)(2 * c) * N + idx];
+            hi[c] = dfield[(int64_t)(2 * c + 1) * N + idx];
+        } else {
+            lo[c] = dlo[c];
+            hi[c] = dhi[c];
+        }
+    }
+}
+
 double orc_hamiltonian(const orc_dyn* dyn, const double* x, const double* p,
                        const double* dlo, const double* dhi)
 {
@@ -208,12 +227,13 @@ static int grid_valid(const orc_grid* g)
 /* Lax-Friedrichs bounds and time step                                       */
 /* ------------------------------------------------------------------------ */
 
-void orc_lf_alpha(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
-                  const double* dhi, double* alpha)
+void orc_lf_alpha_field(const orc_dyn* dyn, const orc_grid* g,
+                        const double* dlo, const double* dhi,
+                        const double* dfield, double* alpha)
 {
     int D = g->ndim;
     int mu = orc_num_ctrl(dyn->kind), md = orc_num_dstb(dyn->kind);
-    double ulo[4], uhi[4], u[4], d[4], f[4], x[4];
+    double ulo[4], uhi[4], u[4], d[4], f[4], x[4], blo[2], bhi[2];
     int j[4];
     orc_ctrl_box(dyn, ulo, uhi);
     for (int i = 0; i < D; i++) alpha[i] = 0.0;
@@ -221,16 +241,23 @@ void orc_lf_alpha(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
     for (int64_t idx = 0; idx < N; idx++) {
         unflatten(g, idx, j);
         for (int i = 0; i < D; i++) x[i] = orc_coord(g, i, j[i]);
+        node_dbox(md, dlo, dhi, dfield, N, idx, blo, bhi);
         for (int vu = 0; vu < (1 << mu); vu++) {
             box_vertex(mu, ulo, uhi, vu, u);
             for (int vd = 0; vd < (1 << md); vd++) {
-                box_vertex(md, dlo, dhi, vd, d);
+                box_vertex(md, blo, bhi, vd, d);
                 orc_dynamics(dyn, x, u, d, f);
                 for (int i = 0; i < D; i++)
                     if (fabs(f[i]) > alpha[i]) alpha[i] = fabs(f[i]);
             }
         }
     }
+}
+
+void orc_lf_alpha(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
+                  const double* dhi, double* alpha)
+{
+    orc_lf_alpha_field(dyn, g, dlo, dhi, NULL, alpha);
 }
 
 double orc_dt(const orc_grid* g, const double* alpha, double cfl)
@@ -296,12 +323,13 @@ void orc_line_derivs(const double* v, int n, double h, int order, double* pm,
 
 /* L(V) at node idx. */
 static double node_op(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
-                      const double* dhi, const double* alpha, int order,
-                      const double* V, int64_t idx)
+                      const double* dhi, const double* dfield,
+                      const double* alpha, int order, const double* V,
+                      int64_t idx)
 {
     int D = g->ndim;
     int j[4];
-    double x[4], pbar[4], diss = 0.0, w[5];
+    double x[4], pbar[4], diss = 0.0, w[5], blo[2], bhi[2];
     unflatten(g, idx, j);
     for (int i = 0; i < D; i++) {
         int64_t s = stride_of(g, i);
@@ -313,34 +341,45 @@ static double node_op(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
         diss += alpha[i] * 0.5 * (pp - pm);
         x[i] = orc_coord(g, i, j[i]);
     }
-    return orc_hamiltonian(dyn, x, pbar, dlo, dhi) + diss;
+    node_dbox(orc_num_dstb(dyn->kind), dlo, dhi, dfield, grid_size(g), idx, blo, bhi);
+    return orc_hamiltonian(dyn, x, pbar, blo, bhi) + diss;
+}
+
+void orc_spatial_op_field(const orc_dyn* dyn, const orc_grid* g,
+                          const double* dlo, const double* dhi,
+                          const double* dfield, const double* alpha, int order,
+                          const double* V, double* L)
+{
+    int64_t N = grid_size(g);
+    for (int64_t idx = 0; idx < N; idx++)
+        L[idx] = node_op(dyn, g, dlo, dhi, dfield, alpha, order, V, idx);
 }
 
 void orc_spatial_op(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
                     const double* dhi, const double* alpha, int order,
                     const double* V, double* L)
 {
-    int64_t N = grid_size(g);
-    for (int64_t idx = 0; idx < N; idx++)
-        L[idx] = node_op(dyn, g, dlo, dhi, alpha, order, V, idx);
+    orc_spatial_op_field(dyn, g, dlo, dhi, NULL, alpha, order, V, L);
 }
 
 /* ------------------------------------------------------------------------ */
 /* Iteration                                                                 */
 /* ------------------------------------------------------------------------ */
 
-double orc_iterate(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
-                   const double* dhi, const double* alpha, double dt,
-                   int order, const double* l, const double* V, double* Vnew)
+double orc_iterate_field(const orc_dyn* dyn, const orc_grid* g,
+                         const double* dlo, const double* dhi,
+                         const double* dfield, const double* alpha, double dt,
+                         int order, const double* l, const double* V,
+                         double* Vnew)
 {
     int64_t N = grid_size(g);
     double* Vhat = (double*)malloc((size_t)N * sizeof(double));
     double* L = (double*)malloc((size_t)N * sizeof(double));
     /* stage 1: forward Euler */
-    orc_spatial_op(dyn, g, dlo, dhi, alpha, order, V, L);
+    orc_spatial_op_field(dyn, g, dlo, dhi, dfield, alpha, order, V, L);
     for (int64_t i = 0; i < N; i++) Vhat[i] = V[i] + dt * L[i];
     /* stage 2: forward Euler from Vhat, average with V, project */
-    orc_spatial_op(dyn, g, dlo, dhi, alpha, order, Vhat, L);
+    orc_spatial_op_field(dyn, g, dlo, dhi, dfield, alpha, order, Vhat, L);
     double r = 0.0;
     for (int64_t i = 0; i < N; i++) {
         double Vtil = Vhat[i] + dt * L[i];
@@ -354,10 +393,18 @@ double orc_iterate(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
     return r;
 }
 
-double orc_iterate_at(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
-                      const double* dhi, const double* alpha, double dt,
-                      int order, const double* l, const double* V,
-                      int64_t idx)
+double orc_iterate(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
+                   const double* dhi, const double* alpha, double dt,
+                   int order, const double* l, const double* V, double* Vnew)
+{
+    return orc_iterate_field(dyn, g, dlo, dhi, NULL, alpha, dt, order, l, V, Vnew);
+}
+
+double orc_iterate_at_field(const orc_dyn* dyn, const orc_grid* g,
+                            const double* dlo, const double* dhi,
+                            const double* dfield, const double* alpha,
+                            double dt, int order, const double* l,
+                            const double* V, int64_t idx)
 {
     /* Stage 2 at idx reads Vhat on the cross-shaped 5-point stencil around
      * idx; build those Vhat values from stage 1 evaluated at each of them. */
@@ -372,7 +419,7 @@ double orc_iterate_at(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
         double vals[1 + 4 * 4];
         int nk = 0;
         keys[nk] = idx;
-        vals[nk++] = V[idx] + dt * node_op(dyn, g, dlo, dhi, alpha, order, V, idx);
+        vals[nk++] = V[idx] + dt * node_op(dyn, g, dlo, dhi, dfield, alpha, order, V, idx);
         for (int i = 0; i < D; i++) {
             int64_t s = stride_of(g, i);
             for (int o = -2; o <= 2; o++) {
@@ -381,7 +428,7 @@ double orc_iterate_at(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
                 if (jj < 0 || jj >= g->n[i]) continue;
                 int64_t k = idx + (int64_t)o * s;
                 keys[nk] = k;
-                vals[nk++] = V[k] + dt * node_op(dyn, g, dlo, dhi, alpha, order, V, k);
+                vals[nk++] = V[k] + dt * node_op(dyn, g, dlo, dhi, dfield, alpha, order, V, k);
             }
         }
         /* L(Vhat) at idx, with the ghost rule applied to Vhat lines. */
@@ -421,11 +468,21 @@ double orc_iterate_at(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
             diss += alpha[i] * 0.5 * (pp - pm);
             x[i] = orc_coord(g, i, j[i]);
         }
-        Lhat = orc_hamiltonian(dyn, x, pbar, dlo, dhi) + diss;
+        double blo[2], bhi[2];
+        node_dbox(orc_num_dstb(dyn->kind), dlo, dhi, dfield, grid_size(g), idx, blo, bhi);
+        Lhat = orc_hamiltonian(dyn, x, pbar, blo, bhi) + diss;
         double Vtil = vals[0] + dt * Lhat;
         double avg = 0.5 * (V[idx] + Vtil);
         return (l[idx] < avg) ? l[idx] : avg;
     }
+}
+
+double orc_iterate_at(const orc_dyn* dyn, const orc_grid* g, const double* dlo,
+                      const double* dhi, const double* alpha, double dt,
+                      int order, const double* l, const double* V,
+                      int64_t idx)
+{
+    return orc_iterate_at_field(dyn, g, dlo, dhi, NULL, alpha, dt, order, l, V, idx);
 }
 
 double orc_residual_band(int64_t N, const double* V, const double* Vnew, double band)
@@ -439,23 +496,33 @@ double orc_residual_band(int64_t N, const double* V, const double* Vnew, double 
     return r;
 }
 
-int orc_solve(const orc_dyn* dyn, const orc_grid* g, const double* l,
-              const double* V0, const double* dlo, const double* dhi,
-              double tol, double band, double cfl, int order, int64_t max_iter,
-              double* V_out, int64_t* iterations, double* residual,
-              double* dt_out, double* alpha_out, double* res_hist,
-              double* max_rise)
+int orc_solve_field(const orc_dyn* dyn, const orc_grid* g, const double* l,
+                    const double* V0, const double* dlo, const double* dhi,
+                    const double* dfield, double tol, double band, double cfl,
+                    int order, int64_t max_iter, double* V_out,
+                    int64_t* iterations, double* residual, double* dt_out,
+                    double* alpha_out, double* res_hist, double* max_rise)
 {
     if (!grid_valid(g) || orc_state_dim(dyn->kind) != g->ndim) return ORC_EINVAL;
     if (!(tol > 0.0) || !(cfl > 0.0 && cfl <= 1.0) || max_iter < 1) return ORC_EINVAL;
     if (!(band >= 0.0)) return ORC_EINVAL;
     if (order != 1 && order != 2) return ORC_EINVAL;
-    for (int c = 0; c < orc_num_dstb(dyn->kind); c++)
-        if (!(dlo[c] <= dhi[c])) return ORC_EINVAL;
-
     int64_t N = grid_size(g);
+    if (dfield) {
+        /* every node's box must be an ordered pair of numbers */
+        for (int c = 0; c < orc_num_dstb(dyn->kind); c++)
+            for (int64_t i = 0; i < N; i++) {
+                double a = dfield[(int64_t)(2 * c) * N + i];
+                double b = dfield[(int64_t)(2 * c + 1) * N + i];
+                if (!(a <= b) || !isfinite(a) || !isfinite(b)) return ORC_EINVAL;
+            }
+    } else {
+        for (int c = 0; c < orc_num_dstb(dyn->kind); c++)
+            if (!(dlo[c] <= dhi[c])) return ORC_EINVAL;
+    }
+
     double alpha[4];
-    orc_lf_alpha(dyn, g, dlo, dhi, alpha);
+    orc_lf_alpha_field(dyn, g, dlo, dhi, dfield, alpha);
     double dt = orc_dt(g, alpha, cfl);
     if (alpha_out)
         for (int i = 0; i < g->ndim; i++) alpha_out[i] = alpha[i];
@@ -473,7 +540,7 @@ int orc_solve(const orc_dyn* dyn, const orc_grid* g, const double* l,
     int64_t k;
     double r = 0.0;
     for (k = 0; k < max_iter; k++) {
-        r = orc_iterate(dyn, g, dlo, dhi, alpha, dt, order, l, V, Vn);
+        r = orc_iterate_field(dyn, g, dlo, dhi, dfield, alpha, dt, order, l, V, Vn);
         if (band > 0.0) r = orc_residual_band(N, V, Vn, band);
         if (max_rise)
             for (int64_t i = 0; i < N; i++)
@@ -499,6 +566,18 @@ int orc_solve(const orc_dyn* dyn, const orc_grid* g, const double* l,
 
 /* ------------------------------------------------------------------------ */
 /* Level transition (Sec. III-C) and refinement mask                         */
+int orc_solve(const orc_dyn* dyn, const orc_grid* g, const double* l,
+              const double* V0, const double* dlo, const double* dhi,
+              double tol, double band, double cfl, int order, int64_t max_iter,
+              double* V_out, int64_t* iterations, double* residual,
+              double* dt_out, double* alpha_out, double* res_hist,
+              double* max_rise)
+{
+    return orc_solve_field(dyn, g, l, V0, dlo, dhi, NULL, tol, band, cfl, order,
+                           max_iter, V_out, iterations, residual, dt_out,
+                           alpha_out, res_hist, max_rise);
+}
+
 /* ------------------------------------------------------------------------ */
 
 int orc_interp(const orc_grid* src, const double* Vs, const orc_grid* dst,

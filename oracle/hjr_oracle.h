@@ -144,6 +144,49 @@ int orc_interp(const orc_grid* src, const double* Vs, const orc_grid* dst,
  * has V >= 0 and another has V < 0.  Returns the number of marked cells. */
 int64_t orc_refine_mask(const orc_grid* g, const double* V, uint8_t* mask);
 
+
+/* ------------------------------------------------------------------------ */
+/* State-dependent disturbance bounds (Sec. II-A: d in D(x); Sec. II-C: the  */
+/* learned bound is a confidence interval at each state).  dfield holds, for */
+/* each disturbance channel c, the lower bounds of every node at            */
+/* dfield[(2c) N ...] and the upper bounds at dfield[(2c + 1) N ...] (N      */
+/* nodes, row-major).  Where these functions take dlo/dhi as well, those    */
+/* are used only when dfield is NULL (then they equal the constant-box      */
+/* functions above).                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* alpha_i = max over nodes x and over the vertices of U x D(x) of |f_i|. */
+void orc_lf_alpha_field(const orc_dyn* dyn, const orc_grid* g,
+                        const double* dlo, const double* dhi,
+                        const double* dfield, double* alpha);
+
+/* L(V) with the Hamiltonian of node x taken over D(x). */
+void orc_spatial_op_field(const orc_dyn* dyn, const orc_grid* g,
+                          const double* dlo, const double* dhi,
+                          const double* dfield, const double* alpha, int order,
+                          const double* V, double* L);
+
+double orc_iterate_field(const orc_dyn* dyn, const orc_grid* g,
+                         const double* dlo, const double* dhi,
+                         const double* dfield, const double* alpha, double dt,
+                         int order, const double* l, const double* V,
+                         double* Vnew);
+
+double orc_iterate_at_field(const orc_dyn* dyn, const orc_grid* g,
+                            const double* dlo, const double* dhi,
+                            const double* dfield, const double* alpha,
+                            double dt, int order, const double* l,
+                            const double* V, int64_t idx);
+
+/* orc_solve with per-node bounds; ORC_EINVAL if a node's pair is not two
+ * finite numbers with lower <= upper. */
+int orc_solve_field(const orc_dyn* dyn, const orc_grid* g, const double* l,
+                    const double* V0, const double* dlo, const double* dhi,
+                    const double* dfield, double tol, double band, double cfl,
+                    int order, int64_t max_iter, double* V_out,
+                    int64_t* iterations, double* residual, double* dt_out,
+                    double* alpha_out, double* res_hist, double* max_rise);
+
 #ifdef __cplusplus
 }
 #endif

@@ -84,6 +84,20 @@ def lib():
         L.orc_interp.argtypes = [gp, dp, gp, dp]
         L.orc_refine_mask.restype = C.c_int64
         L.orc_refine_mask.argtypes = [gp, dp, C.POINTER(C.c_uint8)]
+        L.orc_lf_alpha_field.restype = None
+        L.orc_lf_alpha_field.argtypes = [yp, gp, dp, dp, dp, dp]
+        L.orc_spatial_op_field.restype = None
+        L.orc_spatial_op_field.argtypes = [yp, gp, dp, dp, dp, dp, C.c_int, dp, dp]
+        L.orc_iterate_field.restype = C.c_double
+        L.orc_iterate_field.argtypes = [yp, gp, dp, dp, dp, dp, C.c_double, C.c_int, dp, dp,
+                                        dp]
+        L.orc_iterate_at_field.restype = C.c_double
+        L.orc_iterate_at_field.argtypes = [yp, gp, dp, dp, dp, dp, C.c_double, C.c_int, dp,
+                                           dp, C.c_int64]
+        L.orc_solve_field.restype = C.c_int
+        L.orc_solve_field.argtypes = [yp, gp, dp, dp, dp, dp, dp, C.c_double, C.c_double,
+                                      C.c_double, C.c_int, C.c_int64, dp,
+                                      C.POINTER(C.c_int64), dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -117,11 +131,25 @@ def make_dyn(kind: int, params) -> Dyn:
 def _dbounds(dlo, dhi):
     lo = np.zeros(4)
     hi = np.zeros(4)
+    if dlo is None or dhi is None:
+        return lo, hi
     dlo = np.atleast_1d(np.asarray(dlo, dtype=np.float64))
     dhi = np.atleast_1d(np.asarray(dhi, dtype=np.float64))
     lo[: len(dlo)] = dlo
     hi[: len(dhi)] = dhi
     return lo, hi
+
+
+def _field(grid: Grid, dfield):
+    """Per-node disturbance bounds as the flat (channel, lower/upper, node)
+    array the C code takes (None: the constant box is used)."""
+    if dfield is None:
+        return None, None
+    N = int(np.prod([grid.n[i] for i in range(grid.ndim)]))
+    f = _f64(dfield).reshape(-1)
+    if f.size % (2 * N) != 0:
+        raise ValueError("dfield must hold (channels, 2, N) values")
+    return f, _dp(f)
 
 
 def hamiltonian(dyn: Dyn, x, p, dlo, dhi) -> float:
@@ -140,10 +168,11 @@ def dynamics(dyn: Dyn, x, u, d):
     return f
 
 
-def lf_alpha(dyn: Dyn, grid: Grid, dlo, dhi):
+def lf_alpha(dyn: Dyn, grid: Grid, dlo, dhi, dfield=None):
     lo, hi = _dbounds(dlo, dhi)
+    keep, fp = _field(grid, dfield)
     a = np.zeros(4)
-    lib().orc_lf_alpha(C.byref(dyn), C.byref(grid), _dp(lo), _dp(hi), _dp(a))
+    lib().orc_lf_alpha_field(C.byref(dyn), C.byref(grid), _dp(lo), _dp(hi), fp, _dp(a))
     return a[: grid.ndim]
 
 
@@ -161,37 +190,40 @@ def line_derivs(v, h: float, order: int = 2):
     return pm, pp
 
 
-def spatial_op(dyn, grid, dlo, dhi, alpha, V, order=2):
+def spatial_op(dyn, grid, dlo, dhi, alpha, V, order=2, dfield=None):
     V = _f64(V)
     lo, hi = _dbounds(dlo, dhi)
+    keep, fp = _field(grid, dfield)
     a = np.zeros(4)
     a[: len(alpha)] = alpha
     L = np.zeros_like(V)
-    lib().orc_spatial_op(C.byref(dyn), C.byref(grid), _dp(lo), _dp(hi), _dp(a), order,
-                         _dp(V), _dp(L))
+    lib().orc_spatial_op_field(C.byref(dyn), C.byref(grid), _dp(lo), _dp(hi), fp, _dp(a),
+                               order, _dp(V), _dp(L))
     return L
 
 
-def iterate(dyn, grid, dlo, dhi, alpha, dt_, l, V, order=2):
+def iterate(dyn, grid, dlo, dhi, alpha, dt_, l, V, order=2, dfield=None):
     V = _f64(V)
     l = _f64(l)
     lo, hi = _dbounds(dlo, dhi)
+    keep, fp = _field(grid, dfield)
     a = np.zeros(4)
     a[: len(alpha)] = alpha
     Vn = np.zeros_like(V)
-    r = lib().orc_iterate(C.byref(dyn), C.byref(grid), _dp(lo), _dp(hi), _dp(a), dt_,
-                          order, _dp(l), _dp(V), _dp(Vn))
+    r = lib().orc_iterate_field(C.byref(dyn), C.byref(grid), _dp(lo), _dp(hi), fp, _dp(a),
+                                dt_, order, _dp(l), _dp(V), _dp(Vn))
     return Vn, r
 
 
-def iterate_at(dyn, grid, dlo, dhi, alpha, dt_, l, V, idx, order=2) -> float:
+def iterate_at(dyn, grid, dlo, dhi, alpha, dt_, l, V, idx, order=2, dfield=None) -> float:
     V = _f64(V)
     l = _f64(l)
     lo, hi = _dbounds(dlo, dhi)
+    keep, fp = _field(grid, dfield)
     a = np.zeros(4)
     a[: len(alpha)] = alpha
-    return lib().orc_iterate_at(C.byref(dyn), C.byref(grid), _dp(lo), _dp(hi), _dp(a),
-                                dt_, order, _dp(l), _dp(V), int(idx))
+    return lib().orc_iterate_at_field(C.byref(dyn), C.byref(grid), _dp(lo), _dp(hi), fp,
+                                      _dp(a), dt_, order, _dp(l), _dp(V), int(idx))
 
 
 def residual_band(V, Vnew, band):
@@ -200,12 +232,14 @@ def residual_band(V, Vnew, band):
 
 
 def solve(dyn, grid, l, dlo, dhi, tol=1e-4, V0=None, cfl=0.8, order=2,
-          max_iter=100000, history=False, band=0.0):
+          max_iter=100000, history=False, band=0.0, dfield=None):
     """Returns dict(V, status, iterations, residual, dt, alpha, res_hist, max_rise).
     band > 0 restricts the stop test to nodes with |V| < band before or after
-    the step (see orc_residual_band)."""
+    the step (see orc_residual_band).  dfield: per-node disturbance bounds,
+    shape (channels, 2, N) (lower, upper), used instead of dlo/dhi."""
     l = _f64(l)
     lo, hi = _dbounds(dlo, dhi)
+    keep, fp = _field(grid, dfield)
     V = np.zeros_like(l)
     it = C.c_int64(0)
     res = C.c_double(0)
@@ -217,10 +251,11 @@ def solve(dyn, grid, l, dlo, dhi, tol=1e-4, V0=None, cfl=0.8, order=2,
     if V0 is not None:
         V0 = _f64(V0)
         v0p = _dp(V0)
-    st = lib().orc_solve(C.byref(dyn), C.byref(grid), _dp(l), v0p, _dp(lo), _dp(hi),
-                         float(tol), float(band), float(cfl), int(order), int(max_iter), _dp(V),
-                         C.byref(it), C.byref(res), C.byref(dt_), _dp(a),
-                         _dp(hist) if history else None, C.byref(rise))
+    st = lib().orc_solve_field(C.byref(dyn), C.byref(grid), _dp(l), v0p, _dp(lo), _dp(hi),
+                               fp, float(tol), float(band), float(cfl), int(order),
+                               int(max_iter), _dp(V), C.byref(it), C.byref(res),
+                               C.byref(dt_), _dp(a), _dp(hist) if history else None,
+                               C.byref(rise))
     out = dict(V=V, status=st, iterations=it.value, residual=res.value, dt=dt_.value,
                alpha=a[: grid.ndim].copy(), max_rise=rise.value)
     if history:

@@ -20,7 +20,10 @@ l > 0 inside the constraint set:
   assignment of their four coordinates to the grid axes.
 
 The paper's own workloads come from a simulator and GP-learned bounds that
-are not available; scalar symmetric disturbance bounds [-dbar, dbar] stand in.
+are not available; scalar symmetric disturbance bounds [-dbar, dbar] stand in,
+and for the state-dependent bounds (d in D(x), Sec. II-A, II-C) smooth
+synthetic fields shaped like a GP's pointwise 3-sigma interval around a wind
+bump (see `gp_bound`, `wind_z2d`, `wind_x4d`).
 """
 from __future__ import annotations
 
@@ -64,6 +67,9 @@ class Problem:
     name: str = ""
     band: float = 0.0           # residual band (0 = every node)
     meta: dict = field(default_factory=dict)
+    # per-node disturbance bounds, float64 (channels, 2, N): lower, upper
+    # (None: the constant box dlo, dhi)
+    dfield: np.ndarray | None = None
 
     @property
     def ndim(self) -> int:
@@ -178,3 +184,64 @@ def serve_stream(count=3000, rate=200.0, instances_per_class=4, seed=1,
         reqs.append(dict(seq=i, t=t, instance=inst["instance"], kind=inst["kind"],
                          n=inst["n"], dbar=float(rng.uniform(0.2, 1.0))))
     return insts, reqs
+
+
+# ---------------------------------------------------------------------------
+# State-dependent disturbance bounds (Sec. II-A: d in D(x); Sec. II-C: the
+# bound is a GP's confidence interval at each state).  Layout of a field:
+# float64 array (channels, 2, N), [c, 0] = lower and [c, 1] = upper bound of
+# channel c at every node, nodes row-major like l.
+# ---------------------------------------------------------------------------
+
+def gp_bound(mu, sigma, k=3.0) -> np.ndarray:
+    """One channel's bounds mu -/+ k sigma (the paper's 99.7 % interval is
+    k = 3), as a (1, 2, N) field."""
+    mu = np.asarray(mu, dtype=np.float64).ravel()
+    sigma = np.asarray(sigma, dtype=np.float64).ravel()
+    return np.stack([mu - k * sigma, mu + k * sigma])[None]
+
+
+def constant_field(P: Problem) -> np.ndarray:
+    """The constant box of P written out per node."""
+    N = P.size
+    return np.stack([np.stack([np.full(N, lo), np.full(N, hi)])
+                     for lo, hi in zip(P.dlo, P.dhi)])
+
+
+def wind_z2d(n=101, peak=3.0, z0=0.35, width=0.3, sigma_near=0.1, sigma_far=0.2,
+             z_data=1.5, reach=1.2) -> np.ndarray:
+    """Bound on the vertical model's disturbance after a wind update (Sec. V:
+    a wind whose mean peaks at 3.0 m/s^2 at z = 0.35 m).  Mean: Gaussian bump
+    of that peak at z0; standard deviation sigma_near where the vehicle flew
+    (around z_data), growing to sigma_far away from it; bounds mean -/+ 3
+    sigma.  Depends on z only.  With the defaults every node's interval lies
+    inside [-4.75, 3.44], so hovering stays feasible."""
+    nn = (n, n) if np.isscalar(n) else tuple(n)
+    Z, _ = mesh(nn, Z2D_BOX[0], Z2D_BOX[1])
+    mu = peak * np.exp(-0.5 * ((Z - z0) / width) ** 2)
+    sig = sigma_far - (sigma_far - sigma_near) * np.exp(-0.5 * ((Z - z_data) / reach) ** 2)
+    return gp_bound(mu, sig)
+
+
+def wind_x4d(n=41, peak=0.4, x0=3.0, width=1.2, sigma=0.1, sigma_speed=0.05) -> np.ndarray:
+    """Bound on the x-subsystem's disturbance (on the position rate): mean a
+    Gaussian bump of `peak` at x = x0 (wind near one wall), standard
+    deviation sigma + sigma_speed |vx| / 2 (less data at speed).  Far from the
+    bump at vx = 0 the interval is the paper's initial +-0.3 (sigma = 0.1)."""
+    nn = (n,) * 4 if np.isscalar(n) else tuple(n)
+    G = mesh(nn, X4D_BOX[0], X4D_BOX[1])
+    X, VX = G[0], G[1]
+    mu = peak * np.exp(-0.5 * ((X - x0) / width) ** 2)
+    sig = sigma + sigma_speed * np.abs(VX) / 2.0
+    return gp_bound(mu, sig)
+
+
+def with_field(P: Problem, dfield: np.ndarray, name: str | None = None) -> Problem:
+    """P with per-node bounds; dlo, dhi become the field's extremes (for
+    display only: a field, when present, is what the solvers use)."""
+    f = np.asarray(dfield, dtype=np.float64).reshape(len(P.dlo), 2, P.size)
+    Q = Problem(P.kind, P.params, P.n, P.lo, P.hi, P.l,
+                tuple(float(f[c, 0].min()) for c in range(f.shape[0])),
+                tuple(float(f[c, 1].max()) for c in range(f.shape[0])),
+                tol=P.tol, name=name or P.name, band=P.band, meta=dict(P.meta), dfield=f)
+    return Q
