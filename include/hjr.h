@@ -229,6 +229,26 @@ hjr_status hjr_solve_levels(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* gr
                             uint8_t* const* masks, int64_t* mask_counts,
                             hjr_stats* stats);
 
+/* Safe-set computation with state-dependent disturbance bounds (paper
+ * Sec. II-A: the disturbance ranges over a set D(x) that depends on the
+ * state; Sec. II-C: the learned bound is a confidence interval at every
+ * state).  As hjr_solve_levels, except that level k's disturbance box at
+ * node i comes from the device array dfield[k] of 2 * nch * N_k elements of
+ * the solve's dtype (nch = 1 for QUAD_Z2D and QUAD_X4D, 2 for DI2X2):
+ * dfield[k][2c N_k + i] is the lower and dfield[k][(2c + 1) N_k + i] the
+ * upper bound of channel c at node i.  The Hamiltonian at a node takes its
+ * min over that node's box; the Lax-Friedrichs bound alpha_i is the max of
+ * |f_i| over every node and the vertices of its box.  Every pair must be
+ * two finite numbers with lower <= upper: the fields are checked on the
+ * device before anything else is enqueued, and the call returns EINVAL if
+ * one is not.  The fields are only read and must stay valid until the call
+ * returns.  nlev in 1..4, grids as for hjr_solve_levels; no refinement
+ * masks.  Synchronises o->stream. */
+hjr_status hjr_solve_field(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* grids,
+                           const void* const* l, const void* const* dfield, const void* V0,
+                           double tol, const hjr_opts* o, void* const* V_levels,
+                           hjr_stats* stats);
+
 /* One independent subsystem problem of a batch (decomposition, Sec. III-A). */
 typedef struct hjr_problem {
     hjr_dyn dyn;
@@ -243,6 +263,9 @@ typedef struct hjr_problem {
     int32_t tile_rows[4];   /* per level, 0 = hjr_opts.tile_rows / default */
     double band;            /* residual band of this problem's stop test,
                                0 = every node (hjr_opts.band is not used) */
+    const void* dfield[4];  /* per level: per-node disturbance boxes (device,
+                               layout of hjr_solve_field), or NULL = the
+                               constant boxes d (then d must be valid) */
 } hjr_problem;
 
 /* Bytes of device workspace hjr_solve_batch needs for these problems. */
@@ -252,8 +275,10 @@ hjr_status hjr_batch_workspace_bytes(int32_t n, const hjr_problem* probs,
 /* Solve n independent problems together: every device pass advances all
  * unfinished problems by one RK2 step, so per-launch cost is shared and the
  * chip stays full.  Each problem's result is bit-identical to solving it
- * alone (no arithmetic crosses problems).  results (host, n entries,
- * nullable) receive per-problem stats.  Returns OK if every problem
+ * alone (no arithmetic crosses problems).  Disturbance fields
+ * (hjr_problem.dfield) are checked as in hjr_solve_field before anything is
+ * solved (EINVAL if one is invalid).  results (host, n entries, nullable)
+ * receive per-problem stats.  Returns OK if every problem
  * converged, NOT_CONVERGED if any did not (see results[i].status), or an
  * error.  Synchronises o->stream. */
 hjr_status hjr_solve_batch(int32_t n, const hjr_problem* probs, const hjr_opts* o,
@@ -293,6 +318,10 @@ typedef struct hjr_request {
     int32_t cold;             /* 1 = ignore the resident value, start from l */
     int32_t reserved;
     double band;              /* residual band of the stop test, 0 = every node */
+    const void* dfield;       /* HOST array: per-node disturbance boxes of this
+                                 request (layout of hjr_solve_field, server
+                                 dtype), copied before hjr_server_submit
+                                 returns, or NULL = the constant boxes d */
 } hjr_request;
 
 typedef struct hjr_reply {

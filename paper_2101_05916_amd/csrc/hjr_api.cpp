@@ -223,20 +223,114 @@ hjr_status run_engine(Engine& eng)
     return eng.drain();
 }
 
+// need_d: some level uses the constant boxes d (no disturbance field).
 hjr_status check_job_spec(const hjr_dyn* dyn, int nlev, const hjr_grid* grids, const hjr_dstb* d,
-                          double tol, double band)
+                          double tol, double band, bool need_d = true)
 {
     if (!(band >= 0.0)) return HJR_EINVAL;  // negative or NaN
-    if (!dyn || !grids || !d) return HJR_EINVAL;
+    if (!dyn || !grids || (need_d && !d)) return HJR_EINVAL;
     if (nlev < 1 || nlev > 4) return HJR_EINVAL;
     for (int k = 0; k < nlev; k++) {
         if (!grid_valid(grids[k])) return HJR_EINVAL;
         if (!dyn_valid(*dyn, grids[k])) return HJR_EINVAL;
         if (k > 0 && !same_box(grids[0], grids[k])) return HJR_EINVAL;
     }
-    if (!dstb_valid(*dyn, d)) return HJR_EINVAL;
+    if (need_d && !dstb_valid(*dyn, d)) return HJR_EINVAL;
     if (!(tol > 0.0) || !std::isfinite(tol)) return HJR_EINVAL;
     return HJR_OK;
+}
+
+// Device check of the disturbance fields of a job's levels (EINVAL if a
+// pair is not finite and ordered).
+hjr_status check_fields(Engine& eng, const Job& j)
+{
+    for (int k = 0; k < j.nlev; k++) {
+        if (!j.lev[k].dfield) continue;
+        int64_t bad = 0;
+        hjr_status st = eng.check_field(j.lev[k].dfield, dyn_channels(j.dyn.kind),
+                                        grid_size(j.lev[k].grid), &bad);
+        if (st != HJR_OK) return st;
+        if (bad) return HJR_EINVAL;
+    }
+    return HJR_OK;
+}
+
+// Coarse-to-fine solve of one job, with optional fields per level
+// (dfield == NULL or dfield[k] == NULL: the boxes d).
+hjr_status solve_levels_impl(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* grids,
+                             const void* const* l, const void* const* dfield, const void* V0,
+                             const hjr_dstb* d, double tol, const hjr_opts* o,
+                             void* const* V_levels, uint8_t* const* masks,
+                             int64_t* mask_counts, hjr_stats* stats)
+{
+    const hjr_opts op = resolve(o);
+    if (!opts_valid(op)) return HJR_EINVAL;
+    bool need_d = !dfield;
+    if (dfield && nlev >= 1 && nlev <= 4)
+        for (int k = 0; k < nlev; k++) need_d = need_d || !dfield[k];
+    hjr_status st = check_job_spec(dyn, nlev, grids, d, tol, op.band, need_d);
+    if (st != HJR_OK) return st;
+    if (!l || !V_levels) return HJR_EINVAL;
+    for (int k = 0; k < nlev; k++)
+        if (!l[k] || !V_levels[k]) return HJR_EINVAL;
+
+    const int K = chunk_of(op);
+    const size_t need = job_scratch_bytes(grids, nlev, op.dtype);
+    try {
+        EngineCfg cfg;
+        cfg.dtype = op.dtype;
+        cfg.order = op.order;
+        cfg.cfl = op.cfl;
+        cfg.max_iter = op.max_iter;
+        cfg.K = K;
+        cfg.cap = 1;
+        cfg.flags = op.flags;
+        Session ses;
+        if ((st = ses.open(op, cfg, need)) != HJR_OK) return st;
+        Engine& eng = *ses.eng;
+        Job j;
+        j.dyn = *dyn;
+        std::memset(j.d, 0, sizeof(j.d));
+        if (need_d)
+            for (int c = 0; c < dyn_channels(dyn->kind); c++) j.d[c] = d[c];
+        j.tol = tol;
+        j.band = op.band;
+        j.nlev = nlev;
+        for (int k = 0; k < nlev; k++) {
+            j.lev[k].grid = grids[k];
+            j.lev[k].l = l[k];
+            j.lev[k].V = V_levels[k];
+            j.lev[k].mask = masks ? masks[k] : nullptr;
+            j.lev[k].tile_rows = op.tile_rows;
+            j.lev[k].dfield = dfield ? dfield[k] : nullptr;
+        }
+        j.V0 = V0;
+        if ((st = check_fields(eng, j)) != HJR_OK) {
+            if (st == HJR_EINVAL) ses.clean = true;  // the engine is idle and intact
+            return st;
+        }
+        int64_t Nmax = 0;
+        for (int k = 0; k < nlev; k++) Nmax = std::max(Nmax, grid_size(grids[k]));
+        j.Vhat = ses.ws;
+        j.table = ses.ws + align256(Nmax * elem_size(op.dtype));
+        if ((st = eng.add(&j)) != HJR_OK) return st;
+        if ((st = run_engine(eng)) != HJR_OK) return st;
+        ProbState ps;
+        if ((st = eng.read_state(j.slot, &ps)) != HJR_OK) return st;
+        if (mask_counts) {
+            uint64_t mc[4];
+            if ((st = eng.read_mask_counts(j.slot, mc)) != HJR_OK) return st;
+            for (int k = 0; k < nlev; k++) mask_counts[k] = (int64_t)mc[k];
+        }
+        const double ms = ses.elapsed_ms();
+        fill_stats(stats, j, ps, ms, eng);
+        ses.clean = true;
+        return (hjr_status)j.status;
+    } catch (const std::bad_alloc&) {
+        return HJR_ENOMEM;
+    } catch (...) {
+        return HJR_EDEVICE;
+    }
 }
 
 }  // namespace
@@ -284,65 +378,20 @@ hjr_status hjr_solve_levels(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* gr
                             const hjr_opts* o, void* const* V_levels, uint8_t* const* masks,
                             int64_t* mask_counts, hjr_stats* stats)
 {
-    const hjr_opts op = resolve(o);
-    if (!opts_valid(op)) return HJR_EINVAL;
-    hjr_status st = check_job_spec(dyn, nlev, grids, d, tol, op.band);
-    if (st != HJR_OK) return st;
-    if (!l || !V_levels) return HJR_EINVAL;
-    for (int k = 0; k < nlev; k++)
-        if (!l[k] || !V_levels[k]) return HJR_EINVAL;
+    return solve_levels_impl(dyn, nlev, grids, l, nullptr, V0, d, tol, o, V_levels, masks,
+                             mask_counts, stats);
+}
 
-    const int K = chunk_of(op);
-    const size_t need = job_scratch_bytes(grids, nlev, op.dtype);
-    try {
-        EngineCfg cfg;
-        cfg.dtype = op.dtype;
-        cfg.order = op.order;
-        cfg.cfl = op.cfl;
-        cfg.max_iter = op.max_iter;
-        cfg.K = K;
-        cfg.cap = 1;
-        cfg.flags = op.flags;
-        Session ses;
-        if ((st = ses.open(op, cfg, need)) != HJR_OK) return st;
-        Engine& eng = *ses.eng;
-        Job j;
-        j.dyn = *dyn;
-        std::memset(j.d, 0, sizeof(j.d));
-        for (int c = 0; c < dyn_channels(dyn->kind); c++) j.d[c] = d[c];
-        j.tol = tol;
-        j.band = op.band;
-        j.nlev = nlev;
-        for (int k = 0; k < nlev; k++) {
-            j.lev[k].grid = grids[k];
-            j.lev[k].l = l[k];
-            j.lev[k].V = V_levels[k];
-            j.lev[k].mask = masks ? masks[k] : nullptr;
-            j.lev[k].tile_rows = op.tile_rows;
-        }
-        j.V0 = V0;
-        int64_t Nmax = 0;
-        for (int k = 0; k < nlev; k++) Nmax = std::max(Nmax, grid_size(grids[k]));
-        j.Vhat = ses.ws;
-        j.table = ses.ws + align256(Nmax * elem_size(op.dtype));
-        if ((st = eng.add(&j)) != HJR_OK) return st;
-        if ((st = run_engine(eng)) != HJR_OK) return st;
-        ProbState ps;
-        if ((st = eng.read_state(j.slot, &ps)) != HJR_OK) return st;
-        if (mask_counts) {
-            uint64_t mc[4];
-            if ((st = eng.read_mask_counts(j.slot, mc)) != HJR_OK) return st;
-            for (int k = 0; k < nlev; k++) mask_counts[k] = (int64_t)mc[k];
-        }
-        const double ms = ses.elapsed_ms();
-        fill_stats(stats, j, ps, ms, eng);
-        ses.clean = true;
-        return (hjr_status)j.status;
-    } catch (const std::bad_alloc&) {
-        return HJR_ENOMEM;
-    } catch (...) {
-        return HJR_EDEVICE;
-    }
+hjr_status hjr_solve_field(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* grids,
+                           const void* const* l, const void* const* dfield, const void* V0,
+                           double tol, const hjr_opts* o, void* const* V_levels,
+                           hjr_stats* stats)
+{
+    if (!dfield || nlev < 1 || nlev > 4) return HJR_EINVAL;
+    for (int k = 0; k < nlev; k++)
+        if (!dfield[k]) return HJR_EINVAL;
+    return solve_levels_impl(dyn, nlev, grids, l, dfield, V0, nullptr, tol, o, V_levels,
+                             nullptr, nullptr, stats);
 }
 
 hjr_status hjr_solve_ex(const hjr_dyn* dyn, const hjr_grid* grid, const void* l, const void* V0,
@@ -392,7 +441,9 @@ hjr_status hjr_solve_batch(int32_t n, const hjr_problem* probs, const hjr_opts* 
     if (!opts_valid(op) || n < 1 || !probs) return HJR_EINVAL;
     for (int i = 0; i < n; i++) {
         const hjr_problem& p = probs[i];
-        hjr_status st = check_job_spec(&p.dyn, p.nlev, p.grids, p.d, p.tol, p.band);
+        bool need_d = false;
+        for (int k = 0; k < p.nlev && k < 4; k++) need_d = need_d || !p.dfield[k];
+        hjr_status st = check_job_spec(&p.dyn, p.nlev, p.grids, p.d, p.tol, p.band, need_d);
         if (st != HJR_OK) return st;
         for (int k = 0; k < p.nlev; k++)
             if (!p.l[k] || !p.V[k]) return HJR_EINVAL;
@@ -420,7 +471,10 @@ hjr_status hjr_solve_batch(int32_t n, const hjr_problem* probs, const hjr_opts* 
             Job& j = jobs[i];
             j.dyn = pr.dyn;
             std::memset(j.d, 0, sizeof(j.d));
-            for (int c = 0; c < dyn_channels(pr.dyn.kind); c++) j.d[c] = pr.d[c];
+            bool need_d = false;
+            for (int k = 0; k < pr.nlev; k++) need_d = need_d || !pr.dfield[k];
+            if (need_d)
+                for (int c = 0; c < dyn_channels(pr.dyn.kind); c++) j.d[c] = pr.d[c];
             j.tol = pr.tol;
             j.band = pr.band;
             j.nlev = pr.nlev;
@@ -431,14 +485,23 @@ hjr_status hjr_solve_batch(int32_t n, const hjr_problem* probs, const hjr_opts* 
                 j.lev[k].V = pr.V[k];
                 j.lev[k].mask = nullptr;
                 j.lev[k].tile_rows = pr.tile_rows[k] > 0 ? pr.tile_rows[k] : op.tile_rows;
+                j.lev[k].dfield = pr.dfield[k];
                 Nmax = std::max(Nmax, grid_size(pr.grids[k]));
             }
             j.V0 = pr.V0;
             j.Vhat = p;
             j.table = p + align256(Nmax * elem_size(op.dtype));
             p += job_scratch_bytes(pr.grids, pr.nlev, op.dtype);
-            if ((st = eng.add(&j)) != HJR_OK) return st;
         }
+        // every field is checked before any job starts (no output is written
+        // when one is invalid)
+        for (int i = 0; i < n; i++)
+            if ((st = check_fields(eng, jobs[i])) != HJR_OK) {
+                if (st == HJR_EINVAL) ses.clean = true;  // the engine is idle and intact
+                return st;
+            }
+        for (int i = 0; i < n; i++)
+            if ((st = eng.add(&jobs[i])) != HJR_OK) return st;
         if ((st = run_engine(eng)) != HJR_OK) return st;
         const double ms = ses.elapsed_ms();
         hjr_status all = HJR_OK;

@@ -67,28 +67,40 @@ enum TilePath : int32_t { kPathFlat = 0, kPathPlaneS = 1, kPathPlaneL = 2 };
 
 // Tile families.  Every family has its own stage kernels, so registers and
 // LDS are sized for its tile code alone; a chunk launches one kernel per
-// family present.  Plane families are (model, row stride, ENO order).
+// family present.  Plane families are (model, row stride, ENO order), and
+// (model, row stride) with ENO2 for problems with per-node disturbance
+// bounds (the "F" families; such problems with first-order derivatives take
+// flat tiles).
 enum Family : int32_t {
     kFamFlat = 0,
     kFamZ2dS2, kFamZ2dL2, kFamX4dS2, kFamX4dL2,
     kFamZ2dS1, kFamZ2dL1, kFamX4dS1, kFamX4dL1,
+    kFamZ2dS2F, kFamZ2dL2F, kFamX4dS2F, kFamX4dL2F,
     kNumFam
 };
 
+// Plane families come in groups of four: (Z2D, narrow), (Z2D, wide),
+// (X4D, narrow), (X4D, wide).
+__host__ __device__ constexpr int fam_slot(int f) { return (f - 1) & 3; }
+
 __host__ __device__ constexpr int fam_rs(int f)
 {
-    return (f == kFamZ2dS2 || f == kFamX4dS2 || f == kFamZ2dS1 || f == kFamX4dS1) ? kRowStrideS
-         : (f == kFamFlat) ? 0 : kRowStrideL;
+    return f == kFamFlat ? 0 : ((fam_slot(f) & 1) ? kRowStrideL : kRowStrideS);
 }
 
 __host__ __device__ constexpr int fam_order(int f)
 {
-    return (f >= kFamZ2dS1) ? 1 : 2;
+    return (f >= kFamZ2dS1 && f <= kFamX4dL1) ? 1 : 2;
 }
 
 __host__ __device__ constexpr bool fam_x4d(int f)
 {
-    return f == kFamX4dS2 || f == kFamX4dL2 || f == kFamX4dS1 || f == kFamX4dL1;
+    return f != kFamFlat && fam_slot(f) >= 2;
+}
+
+__host__ __device__ constexpr bool fam_field(int f)
+{
+    return f >= kFamZ2dS2F;
 }
 
 // LDS elements of a plane block of row stride rs (0 for flat tiles).
@@ -142,6 +154,7 @@ struct ProbDesc {
     const void* l;           // constraint
     void* Vhat;              // stage-1 scratch
     void* table;             // per-axis lookup table (g tan(theta) for QUAD_X4D)
+    const void* dfield;      // per-node disturbance boxes (channel, lower/upper, node), or null
     int64_t tile_begin;      // first global tile of this problem
     int64_t ntiles;
 };
@@ -154,12 +167,15 @@ struct ProbDesc {
 #define HJR_CONST __attribute__((address_space(4)))
 typedef const HJR_CONST ProbDesc PDesc;
 
-// Family of a problem's tiles (its model, tile path and ENO order).
+// Family of a problem's tiles (its model, tile path, ENO order and whether
+// it has a disturbance field; the host sends a field with first-order
+// derivatives to flat tiles).
 inline int family_of(const ProbDesc& P)
 {
     if (P.path == kPathFlat) return kFamFlat;
     const bool narrow = P.path == kPathPlaneS, x4 = P.kind == HJR_QUAD_X4D;
-    const int base = P.order == 1 ? kFamZ2dS1 : kFamZ2dS2;  // Z2D S, Z2D L, X4D S, X4D L
+    // first of the group Z2D S, Z2D L, X4D S, X4D L
+    const int base = P.dfield ? kFamZ2dS2F : (P.order == 1 ? kFamZ2dS1 : kFamZ2dS2);
     return base + (x4 ? 2 : 0) + (narrow ? 0 : 1);
 }
 

@@ -157,6 +157,7 @@ size_t Engine::table_bytes(int cap, int K)
     b += 2 * align256(sizeof(uint64_t) * (size_t)cap * (K + 1) * kResSubs);
     b += 2 * align256(sizeof(double) * (size_t)cap * K);
     b += align256(sizeof(uint64_t) * 4 * cap);
+    b += align256(sizeof(uint64_t));  // field-check counter
     return b;
 }
 
@@ -190,6 +191,7 @@ hjr_status Engine::init(hipStream_t stream, void* arena)
     for (int q = 0; q < 2; q++) d_res_[q] = (uint64_t*)take(sizeof(uint64_t) * (size_t)cap * (K + 1) * kResSubs);
     for (int q = 0; q < 2; q++) d_compact_[q] = (double*)take(sizeof(double) * (size_t)cap * K);
     d_mask_counts_ = (uint64_t*)take(sizeof(uint64_t) * 4 * cap);
+    d_check_ = (uint64_t*)take(sizeof(uint64_t));
 
     for (int q = 0; q < 2; q++) {
         HJR_TRY(hipHostMalloc((void**)&h_desc_[q], desc_bytes_, hipHostMallocDefault));
@@ -250,6 +252,17 @@ hjr_status Engine::reset(const EngineCfg& c)
     return HJR_OK;
 }
 
+hjr_status Engine::check_field(const void* f, int nch, int64_t N, int64_t* bad)
+{
+    uint64_t h = 0;
+    HJR_TRY(launch_fill_u64(stream_, d_check_, 1, 0));
+    HJR_TRY(launch_field_check(stream_, cfg_.dtype, f, nch, N, d_check_));
+    HJR_TRY(hipMemcpyAsync(&h, d_check_, sizeof(h), hipMemcpyDeviceToHost, stream_));
+    HJR_TRY(hipStreamSynchronize(stream_));
+    *bad = (int64_t)h;
+    return HJR_OK;
+}
+
 int Engine::free_slots() const
 {
     int n = 0;
@@ -287,6 +300,7 @@ void Engine::fill_desc(const Job* j, ProbDesc& P) const
     P.l = L.l;
     P.Vhat = j->Vhat;
     P.table = j->table;
+    P.dfield = L.dfield;
     const int D = g.ndim;
     for (int a = 0; a < D; a++) {
         P.hih[a] = 0.5 / P.h[a];
@@ -304,6 +318,10 @@ void Engine::fill_desc(const Job* j, ProbDesc& P) const
         hc[1] = P.hih[0] * P.h[1];
         hc[2] = (std::max(ku_lo, ku_hi) + dl - p[1]) * P.hih[1];
         hc[3] = (std::min(ku_lo, ku_hi) + dh - p[1]) * P.hih[1];
+        // with a per-node disturbance box the bound is added at the node
+        hc[4] = (std::max(ku_lo, ku_hi) - p[1]) * P.hih[1];
+        hc[5] = (std::min(ku_lo, ku_hi) - p[1]) * P.hih[1];
+        hc[6] = P.hih[1];
     } else if (P.kind == HJR_QUAD_X4D) {
         const double g_ = p[0], d1 = p[1], d0 = p[2], n0 = p[3], sm = p[4];
         hc[0] = P.hih[0] * P.lo[1];
@@ -316,6 +334,7 @@ void Engine::fill_desc(const Job* j, ProbDesc& P) const
         hc[7] = d0 * P.hih[3] * P.lo[2];
         hc[8] = d0 * P.hih[3] * P.h[2];
         hc[9] = n0 * sm * P.hih[3];
+        hc[10] = P.hih[0];  // scales a per-node disturbance bound
         (void)g_;
     }
     for (int i = 0; i < 16; i++) P.hc_f[i] = (float)P.hc_d[i];
@@ -323,8 +342,10 @@ void Engine::fill_desc(const Job* j, ProbDesc& P) const
     // else flat tiles of kTile consecutive nodes
     P.path = kPathFlat;
     P.ntiles = (P.N + kTile - 1) / kTile;
+    // (per-node disturbance boxes have plane families for ENO2 only)
     const bool plane_kind = (P.kind == HJR_QUAD_Z2D || P.kind == HJR_QUAD_X4D) &&
-                            !(cfg_.flags & HJR_FLAG_FLAT_TILES);
+                            !(cfg_.flags & HJR_FLAG_FLAT_TILES) &&
+                            !(P.dfield && P.order != 2);
     // plane tiles address with 32-bit byte offsets
     const bool fits32 = (double)P.N * (double)elem_size(cfg_.dtype) < 4294967296.0;
     if (plane_kind && fits32 && (D == 2 || D == 4)) {

@@ -40,6 +40,7 @@ struct Level {
     void* V = nullptr;
     uint8_t* mask = nullptr;  // optional refinement-mask output
     int tile_rows = 0;        // LDS tile height, 0 = default
+    const void* dfield = nullptr;  // per-node disturbance boxes, or null (Job::d)
 };
 
 // One solve job: a chain of 1..4 grid levels of one subsystem.
@@ -98,6 +99,11 @@ public:
     bool busy() const { return running_ > 0; }
     int free_slots() const;
     int running() const { return running_; }
+
+    // Number of nodes of a disturbance field (nch channels over N nodes, in
+    // the engine's dtype) whose box is not a finite ordered pair (sync; the
+    // engine must be idle).
+    hjr_status check_field(const void* f, int nch, int64_t N, int64_t* bad);
 
     // Copy the per-slot device state (alpha, dt) of a slot to *out (sync).
     hjr_status read_state(int slot, ProbState* out);
@@ -171,6 +177,7 @@ private:
     uint64_t* d_res_[2] = {nullptr, nullptr};
     double* d_compact_[2] = {nullptr, nullptr};
     uint64_t* d_mask_counts_ = nullptr;  // [cap][4]
+    uint64_t* d_check_ = nullptr;        // counter of check_field
     // pinned host mirrors (descriptors + order list, one copy)
     ProbDesc* h_desc_[2] = {nullptr, nullptr};
     hipEvent_t desc_ev_[2] = {nullptr, nullptr};

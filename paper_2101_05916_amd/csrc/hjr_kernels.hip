@@ -191,21 +191,23 @@ __global__ __launch_bounds__(64) void k_epilogue(ChunkArgs A)
 // per-level set-up: Lax-Friedrichs bounds, dt, lookup table
 // ------------------------------------------------------------------------
 
-// f_i at node x for control vertex vu and disturbance vertex vd, in double.
-__device__ void dyn_f(const ProbDesc& P, const double* x, int vu, int vd, double* f)
+// f_i at node x for control vertex vu and disturbance vertex vd of the box
+// [dl[c], dh[c]] per channel, in double.
+__device__ void dyn_f(const ProbDesc& P, const double* x, int vu, int vd, const double* dl,
+                      const double* dh, double* f)
 {
     const double* p = P.par;
     switch (P.kind) {
     case HJR_QUAD_Z2D: {
         const double u = (vu & 1) ? p[3] : p[2];
-        const double d = (vd & 1) ? P.dhi[0] : P.dlo[0];
+        const double d = (vd & 1) ? dh[0] : dl[0];
         f[0] = x[1];
         f[1] = p[0] * u - p[1] + d;
         break;
     }
     case HJR_QUAD_X4D: {
         const double S = (vu & 1) ? p[4] : -p[4];
-        const double d = (vd & 1) ? P.dhi[0] : P.dlo[0];
+        const double d = (vd & 1) ? dh[0] : dl[0];
         f[0] = x[1] + d;
         f[1] = p[0] * tan(x[2]);
         f[2] = -p[1] * x[2] + x[3];
@@ -216,8 +218,8 @@ __device__ void dyn_f(const ProbDesc& P, const double* x, int vu, int vd, double
         const int za = (int)p[8], va = (int)p[9], zb = (int)p[10], vb = (int)p[11];
         const double ua = (vu & 1) ? p[3] : p[2];
         const double ub = (vu & 2) ? p[7] : p[6];
-        const double da = (vd & 1) ? P.dhi[0] : P.dlo[0];
-        const double db = (vd & 2) ? P.dhi[1] : P.dlo[1];
+        const double da = (vd & 1) ? dh[0] : dl[0];
+        const double db = (vd & 2) ? dh[1] : dl[1];
         f[za] = x[va];
         f[va] = p[0] * ua - p[1] + da;
         f[zb] = x[vb];
@@ -229,12 +231,17 @@ __device__ void dyn_f(const ProbDesc& P, const double* x, int vu, int vd, double
     }
 }
 
+// alpha_i = max over nodes and over the vertices of the control box and of
+// the node's disturbance box (the constant one, or the field's) of |f_i|.
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_alpha(ProbDesc P, ProbState* st)
 {
     __shared__ uint64_t red[kBlock / 64];
     const int D = P.ndim;
     const int nu = (P.kind == HJR_DI2X2) ? 4 : 2;
     const int nd = (P.kind == HJR_DI2X2) ? 4 : 2;
+    const int nch = (P.kind == HJR_DI2X2) ? 2 : 1;
+    const T* fld = (const T*)P.dfield;
     uint64_t m[4] = {0, 0, 0, 0};
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < P.N;
          idx += (int64_t)gridDim.x * blockDim.x) {
@@ -245,10 +252,17 @@ __global__ __launch_bounds__(kBlock) void k_alpha(ProbDesc P, ProbState* st)
             q /= P.n[a];
             x[a] = P.lo[a] + (double)j * P.h[a];
         }
+        double dl[2] = {P.dlo[0], P.dlo[1]}, dh[2] = {P.dhi[0], P.dhi[1]};
+        if (fld) {
+            for (int c = 0; c < nch; c++) {
+                dl[c] = (double)fld[(int64_t)(2 * c) * P.N + idx];
+                dh[c] = (double)fld[(int64_t)(2 * c + 1) * P.N + idx];
+            }
+        }
         for (int vu = 0; vu < nu; vu++)
             for (int vd = 0; vd < nd; vd++) {
                 double f[4] = {0, 0, 0, 0};
-                dyn_f(P, x, vu, vd, f);
+                dyn_f(P, x, vu, vd, dl, dh, f);
                 for (int a = 0; a < D; a++) m[a] = umax64(m[a], dbits(fabs(f[a])));
             }
     }
@@ -309,6 +323,28 @@ __global__ __launch_bounds__(kBlock) void k_fill_u64(uint64_t* p, int64_t n, uin
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+// Number of entries of a disturbance field (nch channels, N nodes, lower
+// bounds then upper bounds per channel) whose pair is not two finite numbers
+// with lower <= upper, added to *counter.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_field_check(const T* f, int nch, int64_t N,
+                                                        unsigned long long* counter)
+{
+    __shared__ unsigned long long cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    unsigned long long bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)nch * N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = i / N, k = i - c * N;
+        const double lo = (double)f[2 * c * N + k], hi = (double)f[(2 * c + 1) * N + k];
+        if (!(lo <= hi) || !isfinite(lo) || !isfinite(hi)) bad++;
+    }
+    if (bad) atomicAdd(&cnt, bad);
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt) atomicAdd(counter, cnt);
 }
 
 // ------------------------------------------------------------------------
@@ -461,6 +497,10 @@ static hipError_t launch_stage_t(hipStream_t s, int fam, const ChunkArgs& a, int
     case kFamZ2dL1: hipLaunchKernelGGL((k_stage<T, STAGE, kFamZ2dL1>), g, b, 0, s, a); break;
     case kFamX4dS1: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dS1>), g, b, 0, s, a); break;
     case kFamX4dL1: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dL1>), g, b, 0, s, a); break;
+    case kFamZ2dS2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamZ2dS2F>), g, b, 0, s, a); break;
+    case kFamZ2dL2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamZ2dL2F>), g, b, 0, s, a); break;
+    case kFamX4dS2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dS2F>), g, b, 0, s, a); break;
+    case kFamX4dL2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dL2F>), g, b, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -480,7 +520,10 @@ hipError_t launch_level_setup(hipStream_t s, int dtype, const ProbDesc& P, ProbS
     hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, s, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_alpha, dim3(grid_for(P.N, 1024)), dim3(kBlock), 0, s, P, st);
+    if (dtype == HJR_F32)
+        hipLaunchKernelGGL((k_alpha<float>), dim3(grid_for(P.N, 1024)), dim3(kBlock), 0, s, P, st);
+    else
+        hipLaunchKernelGGL((k_alpha<double>), dim3(grid_for(P.N, 1024)), dim3(kBlock), 0, s, P, st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int g = grid_for(P.ndim >= 3 ? P.n[2] : 1, 64);
@@ -557,6 +600,19 @@ hipError_t launch_mask(hipStream_t s, int dtype, const hjr_grid& g, const void* 
     return hipGetLastError();
 }
 
+hipError_t launch_field_check(hipStream_t s, int dtype, const void* f, int nch, int64_t N,
+                              uint64_t* counter)
+{
+    const int g = grid_for((int64_t)nch * N, 4096);
+    if (dtype == HJR_F32)
+        hipLaunchKernelGGL((k_field_check<float>), dim3(g), dim3(kBlock), 0, s, (const float*)f,
+                           nch, N, (unsigned long long*)counter);
+    else
+        hipLaunchKernelGGL((k_field_check<double>), dim3(g), dim3(kBlock), 0, s, (const double*)f,
+                           nch, N, (unsigned long long*)counter);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(hipStream_t s, uint64_t* p, int64_t n, uint64_t value)
 {
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 1024)), dim3(kBlock), 0, s, p, n, value);
@@ -575,7 +631,11 @@ static const void* stage_kernel(int fam)
     case kFamZ2dS1: return (const void*)k_stage<T, STAGE, kFamZ2dS1>;
     case kFamZ2dL1: return (const void*)k_stage<T, STAGE, kFamZ2dL1>;
     case kFamX4dS1: return (const void*)k_stage<T, STAGE, kFamX4dS1>;
-    default: return (const void*)k_stage<T, STAGE, kFamX4dL1>;
+    case kFamX4dL1: return (const void*)k_stage<T, STAGE, kFamX4dL1>;
+    case kFamZ2dS2F: return (const void*)k_stage<T, STAGE, kFamZ2dS2F>;
+    case kFamZ2dL2F: return (const void*)k_stage<T, STAGE, kFamZ2dL2F>;
+    case kFamX4dS2F: return (const void*)k_stage<T, STAGE, kFamX4dS2F>;
+    default: return (const void*)k_stage<T, STAGE, kFamX4dL2F>;
     }
 }
 

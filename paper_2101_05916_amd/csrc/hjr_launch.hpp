@@ -30,6 +30,11 @@ hipError_t launch_interp(hipStream_t s, int dtype, const hjr_grid& src, const vo
 hipError_t launch_mask(hipStream_t s, int dtype, const hjr_grid& g, const void* V,
                        uint8_t* mask, uint64_t* counter);
 
+// Count the nodes of a disturbance field (nch channels of N lower then N
+// upper bounds) whose pair is not finite and ordered; adds to *counter.
+hipError_t launch_field_check(hipStream_t s, int dtype, const void* f, int nch, int64_t N,
+                              uint64_t* counter);
+
 // Fill n 64-bit words with value.
 hipError_t launch_fill_u64(hipStream_t s, uint64_t* p, int64_t n, uint64_t value);
 

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -57,6 +58,7 @@ struct Ticket {
     uint64_t id = 0;
     hjr_request req;
     std::vector<char> l_host;  // copy of req.l
+    std::vector<char> f_host;  // copy of req.dfield (empty: the boxes req.d)
     Clock::time_point t_submit, t_admit;
     bool admitted = false;
     bool done = false;
@@ -66,8 +68,21 @@ struct Ticket {
     void* V_work = nullptr;
     void* Vhat = nullptr;
     void* table = nullptr;
+    void* field = nullptr;     // device copy of f_host while running
     size_t work_bytes = 0;
 };
+
+// Whether every (lower, upper) pair of a host field is finite and ordered.
+template <typename T>
+bool field_ok(const T* f, int nch, int64_t N)
+{
+    for (int c = 0; c < nch; c++)
+        for (int64_t i = 0; i < N; i++) {
+            const double lo = (double)f[2 * c * N + i], hi = (double)f[(2 * c + 1) * N + i];
+            if (!(lo <= hi) || !std::isfinite(lo) || !std::isfinite(hi)) return false;
+        }
+    return true;
+}
 
 }  // namespace
 
@@ -179,7 +194,9 @@ struct hjr_server {
         give(t.Vhat, vb);
         const int64_t n2 = I.grid.ndim >= 3 ? I.grid.n[2] : 1;
         give(t.table, n2 * esz());
-        t.V_work = t.Vhat = t.table = nullptr;
+        if (t.field) give(t.field, t.f_host.size());
+        t.f_host.clear();
+        t.V_work = t.Vhat = t.table = t.field = nullptr;
         I.busy = false;
         pending[I.id]--;
         I.last_use = ++use_clock;
@@ -211,7 +228,8 @@ struct hjr_server {
                 continue;
             }
             const hjr_grid& g = t.req.grid;
-            const size_t need = work_bytes(g) + (known ? 0 : instance_bytes(g));
+            const size_t fbytes = t.f_host.empty() ? 0 : align256(t.f_host.size());
+            const size_t need = work_bytes(g) + fbytes + (known ? 0 : instance_bytes(g));
             if (!make_room(need, iid, !eng->busy())) {
                 blocked.push_back(iid);
                 ++it;
@@ -254,6 +272,19 @@ struct hjr_server {
                 fatal = HJR_ENOMEM;
                 return;
             }
+            if (!t.f_host.empty()) {
+                t.field = take(t.f_host.size());
+                if (!t.field) {
+                    fatal = HJR_ENOMEM;
+                    return;
+                }
+                if (hipMemcpyAsync(t.field, t.f_host.data(), t.f_host.size(), hipMemcpyHostToDevice,
+                                   stream) != hipSuccess ||
+                    hipStreamSynchronize(stream) != hipSuccess) {
+                    fatal = HJR_EDEVICE;
+                    return;
+                }
+            }
             auto job = std::make_unique<Job>();
             job->dyn = t.req.dyn;
             std::memset(job->d, 0, sizeof(job->d));
@@ -265,6 +296,7 @@ struct hjr_server {
             job->lev[0].l = I.l;
             job->lev[0].V = t.V_work;
             job->lev[0].mask = nullptr;
+            job->lev[0].dfield = t.field;
             const bool warm = I.has_value && !t.req.cold;
             job->V0 = warm ? I.V_res : nullptr;
             job->Vhat = t.Vhat;
@@ -392,8 +424,10 @@ hjr_status hjr_server_submit(hjr_server* s, const hjr_request* req, uint64_t* ti
     if (!s || !req || !ticket) return HJR_EINVAL;
     const hjr_grid& g = req->grid;
     if (!grid_valid(g) || !dyn_valid(req->dyn, g)) return HJR_EINVAL;
-    for (int c = 0; c < dyn_channels(req->dyn.kind); c++)
-        if (!(req->d[c].lo <= req->d[c].hi)) return HJR_EINVAL;
+    const int nch = dyn_channels(req->dyn.kind);
+    if (!req->dfield)
+        for (int c = 0; c < nch; c++)
+            if (!(req->d[c].lo <= req->d[c].hi)) return HJR_EINVAL;
     if (!(req->tol > 0.0)) return HJR_EINVAL;
     if (!(req->band >= 0.0)) return HJR_EINVAL;
     std::unique_ptr<Ticket> t(new Ticket());
@@ -401,6 +435,16 @@ hjr_status hjr_server_submit(hjr_server* s, const hjr_request* req, uint64_t* ti
     std::memset(&t->reply, 0, sizeof(t->reply));
     t->t_submit = Clock::now();
     const size_t bytes = grid_size(g) * s->esz();
+    const size_t fbytes = req->dfield ? 2 * (size_t)nch * bytes : 0;
+    if (req->dfield) {
+        const bool ok = s->cfg.dtype == HJR_F32
+                            ? field_ok((const float*)req->dfield, nch, grid_size(g))
+                            : field_ok((const double*)req->dfield, nch, grid_size(g));
+        if (!ok) return HJR_EINVAL;
+        t->f_host.resize(fbytes);
+        std::memcpy(t->f_host.data(), req->dfield, fbytes);
+    }
+    t->req.dfield = nullptr;
     std::lock_guard<std::mutex> lk(s->m);
     if (s->fatal != HJR_OK) return s->fatal;
     // an instance keeps its grid and model; its first request brings l
@@ -415,7 +459,8 @@ hjr_status hjr_server_submit(hjr_server* s, const hjr_request* req, uint64_t* ti
         return HJR_EINVAL;
     }
     const size_t table = Engine::table_bytes(s->cfg.max_active, s->cfg.chunk);
-    if (align256(table) + s->instance_bytes(g) + s->work_bytes(g) > s->budget) return HJR_ENOMEM;
+    if (align256(table) + s->instance_bytes(g) + s->work_bytes(g) + align256(fbytes) > s->budget)
+        return HJR_ENOMEM;
     if (req->l) {
         t->l_host.resize(bytes);
         std::memcpy(t->l_host.data(), req->l, bytes);
@@ -508,6 +553,7 @@ hjr_status hjr_server_destroy(hjr_server* s)
         if (t.V_work) (void)hipFree(t.V_work);
         if (t.Vhat) (void)hipFree(t.Vhat);
         if (t.table) (void)hipFree(t.table);
+        if (t.field) (void)hipFree(t.field);
     }
     (void)hipStreamDestroy(s->stream);
     delete s;

@@ -221,11 +221,53 @@ struct HamZ2D {
         const T vzh = c0 + (T)j1 * c1;  // (0.5/h0) vz
         return sum[0] * vzh + sum[1] * (sum[1] >= T(0) ? cpos : cneg);
     }
-    // plane tiles: no per-row table
+    // per-node data: none (no per-row table)
+    typedef T Node;
     __device__ __forceinline__ T row_coef(int) const { return T(0); }
+    __device__ __forceinline__ Node node_b(int, uint32_t) const { return T(0); }
+    __device__ __forceinline__ Node node_i(int, int64_t) const { return T(0); }
     __device__ __forceinline__ T eval(const T* sum, int j0, int j1, int j2, int j3, T) const
     {
         return (*this)(sum, j0, j1, j2, j3);
+    }
+};
+
+// The same model with a per-node disturbance box [lo(x), hi(x)] (d in D(x),
+// paper Sec. II-A), read from the field at P.dfield: lower bounds of the N
+// nodes, then upper bounds.  hc[4] = (max(k u) - g) hih1, hc[5] = (min(k u)
+// - g) hih1, hc[6] = hih1.
+template <typename T>
+struct HamZ2DF {
+    T c0, c1, kpos, kneg, h1;
+    const T* flo;
+    const T* fhi;
+    struct Node {
+        T dl, dh;
+    };
+    __device__ void init(PDesc& P)
+    {
+        const HJR_CONST T* hc = Prec<T>::hc(P);
+        c0 = hc[0];
+        c1 = hc[1];
+        kpos = hc[4];
+        kneg = hc[5];
+        h1 = hc[6];
+        flo = (const T*)P.dfield;
+        fhi = flo + P.N;
+    }
+    __device__ __forceinline__ Node node_b(int, uint32_t vb) const
+    {
+        return Node{gld1<T>(flo, vb), gld1<T>(fhi, vb)};
+    }
+    __device__ __forceinline__ Node node_i(int, int64_t idx) const
+    {
+        return Node{ld64(flo, idx), ld64(fhi, idx)};
+    }
+    __device__ __forceinline__ T eval(const T* sum, int, int j1, int, int, Node nd) const
+    {
+        const T vzh = c0 + (T)j1 * c1;  // (0.5/h0) vz
+        const T s1 = sum[1];
+        return sum[0] * vzh + s1 * (s1 >= T(0) ? kpos + nd.dl * h1 : kneg + nd.dh * h1);
     }
 };
 
@@ -267,14 +309,71 @@ struct HamX4D {
     {
         return eval(sum, j0, j1, j2, j3, row_coef(j2));
     }
+    // per-node data: the row coefficient
+    typedef T Node;
+    __device__ __forceinline__ Node node_b(int j2, uint32_t) const { return row_coef(j2); }
+    __device__ __forceinline__ Node node_i(int j2, int64_t) const { return row_coef(j2); }
+};
+
+// The x-subsystem with a per-node disturbance box on x' (field layout as for
+// HamZ2DF); hc[10] = hih0.
+template <typename T>
+struct HamX4DF {
+    T c0, c1, h0, A, B, C, D, E, n0s;
+    const T* gts;
+    const T* flo;
+    const T* fhi;
+    struct Node {
+        T g, dl, dh;
+    };
+    __device__ void init(PDesc& P)
+    {
+        const HJR_CONST T* hc = Prec<T>::hc(P);
+        c0 = hc[0];
+        c1 = hc[1];
+        A = hc[4];
+        B = hc[5];
+        C = hc[6];
+        D = hc[7];
+        E = hc[8];
+        n0s = hc[9];
+        h0 = hc[10];
+        gts = (const T*)P.table;
+        flo = (const T*)P.dfield;
+        fhi = flo + P.N;
+    }
+    __device__ __forceinline__ Node node_b(int j2, uint32_t vb) const
+    {
+        return Node{ld32(gts, (uint32_t)j2), gld1<T>(flo, vb), gld1<T>(fhi, vb)};
+    }
+    __device__ __forceinline__ Node node_i(int j2, int64_t idx) const
+    {
+        return Node{ld32(gts, (uint32_t)j2), ld64(flo, idx), ld64(fhi, idx)};
+    }
+    __device__ __forceinline__ T eval(const T* sum, int, int j1, int j2, int j3, Node nd) const
+    {
+        const T cvx = c0 + (T)j1 * c1;
+        const T tw = A + (T)j3 * B - (T)j2 * C;
+        const T t3 = D + (T)j2 * E;
+        const T s0 = sum[0];
+        return s0 * (cvx + (s0 >= T(0) ? nd.dl : nd.dh) * h0) + sum[1] * nd.g + sum[2] * tw -
+               sum[3] * t3 + n0s * fabs(sum[3]);
+    }
 };
 
 // Two independent vertical models on a permutation of the axes (test model).
-template <typename T>
+// FIELD: channel c's box at node x is [f[2c N + x], f[(2c + 1) N + x]] of
+// the field at P.dfield; else the constant boxes P.dlo, P.dhi.
+template <typename T, bool FIELD = false>
 struct HamDI2X2 {
     int za, va, zb, vb;
     T ga, kalo, kahi, dalo, dahi, gb, kblo, kbhi, dblo, dbhi;
     T hih[4], lo[4], h[4];
+    const T* f;
+    int64_t N;
+    struct Node {
+        T al, ah, bl, bh;
+    };
     __device__ void init(PDesc& P)
     {
         ga = (T)P.par[1];
@@ -291,6 +390,8 @@ struct HamDI2X2 {
         dahi = (T)P.dhi[0];
         dblo = (T)P.dlo[1];
         dbhi = (T)P.dhi[1];
+        f = (const T*)P.dfield;
+        N = P.N;
         for (int a = 0; a < 4; a++) {
             hih[a] = Prec<T>::hih(P)[a];
             lo[a] = Prec<T>::lo(P)[a];
@@ -301,7 +402,13 @@ struct HamDI2X2 {
     {
         return i == 0 ? v[0] : (i == 1 ? v[1] : (i == 2 ? v[2] : v[3]));
     }
-    __device__ __forceinline__ T operator()(const T* sum, int j0, int j1, int j2, int j3) const
+    __device__ __forceinline__ Node node_i(int, int64_t idx) const
+    {
+        if (FIELD)
+            return Node{ld64(f, idx), ld64(f, N + idx), ld64(f, 2 * N + idx), ld64(f, 3 * N + idx)};
+        return Node{dalo, dahi, dblo, dbhi};
+    }
+    __device__ __forceinline__ T eval(const T* sum, int j0, int j1, int j2, int j3, Node nd) const
     {
         const int jj[4] = {j0, j1, j2, j3};
         T p[4], x[4];
@@ -311,8 +418,8 @@ struct HamDI2X2 {
         }
         const T pva = pick(p, va), pvb = pick(p, vb);
         return pick(p, za) * pick(x, va) - ga * pva + fmax(kalo * pva, kahi * pva) +
-               fmin(dalo * pva, dahi * pva) + pick(p, zb) * pick(x, vb) - gb * pvb +
-               fmax(kblo * pvb, kbhi * pvb) + fmin(dblo * pvb, dbhi * pvb);
+               fmin(nd.al * pva, nd.ah * pva) + pick(p, zb) * pick(x, vb) - gb * pvb +
+               fmax(kblo * pvb, kbhi * pvb) + fmin(nd.bl * pvb, nd.bh * pvb);
     }
 };
 
@@ -402,9 +509,9 @@ __device__ uint64_t tile_flat(PDesc& P, PState& S, int64_t tile)
             L += ah[a] * dif;
         }
         if (D == 2)
-            L += ham(sum, j[0], j[1], 0, 0);
+            L += ham.eval(sum, j[0], j[1], 0, 0, ham.node_i(0, idx));
         else
-            L += ham(sum, j[0], j[1], j[2], j[3]);
+            L += ham.eval(sum, j[0], j[1], j[2], j[3], ham.node_i(j[2], idx));
         finish_node<T, STAGE>(P, (int64_t)idx, c, L, dt, rmax);
     }
     return rmax;
@@ -568,12 +675,12 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
             const int rr = (int)fdiv((uint32_t)e, P.div_last);
             const int cc = e - rr * nc;
             T w[8];
-            T rc = T(0);
             if (D == 4) {
 #pragma unroll
                 for (int qq = 0; qq < 8; qq++) w[qq] = gld1<T>(nb[qq], vb);
-                rc = ham.row_coef(r0 + rr);
             }
+            // per-node Hamiltonian data (row coefficient, disturbance box)
+            const typename Ham::Node nd = ham.node_b(r0 + rr, vb);
             T vo = T(0), lvv = T(0);
             if (STAGE == 2) {
                 vo = gld1<T>(vout, vb);
@@ -598,9 +705,9 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
                 if (edge1) ghost_fix<T>(i1, P.n[1], c, m2, m1, p1, p2);
                 eno_sd<T, ORDER>(m2, m1, c, p1, p2, sum[1], dif);
                 L += ah[1] * dif;
-                L += ham.eval(sum, i0, i1, r0 + rr, cc, rc);
+                L += ham.eval(sum, i0, i1, r0 + rr, cc, nd);
             } else {
-                L += ham.eval(sum, r0 + rr, cc, 0, 0, rc);
+                L += ham.eval(sum, r0 + rr, cc, 0, 0, nd);
             }
             if (STAGE == 1) {
                 if (live) gst1<T>(c + dt * L, vout, vb);
@@ -809,19 +916,35 @@ __device__ uint64_t tile_plane_q(PDesc& P, PState& S, uint32_t tile, T* lds)
     return rmax;
 }
 
-// One tile of a family (see Family): flat tiles dispatch on the model at run
-// time, plane families are fixed at compile time.
+// One tile of a family (see Family): flat tiles dispatch on the model (and
+// on whether the problem has a disturbance field) at run time, plane
+// families are fixed at compile time.
 template <typename T, int STAGE, int FAM>
 __device__ __forceinline__ uint64_t run_tile(PDesc& P, PState& S, uint32_t tile,
                                              T* lds)
 {
     if constexpr (FAM == kFamFlat) {
+        if (P.dfield) {
+            switch (P.kind) {
+            case HJR_QUAD_Z2D: return tile_flat<T, 2, HamZ2DF<T>, STAGE>(P, S, tile);
+            case HJR_QUAD_X4D: return tile_flat<T, 4, HamX4DF<T>, STAGE>(P, S, tile);
+            case HJR_DI2X2: return tile_flat<T, 4, HamDI2X2<T, true>, STAGE>(P, S, tile);
+            default: return 0;
+            }
+        }
         switch (P.kind) {
         case HJR_QUAD_Z2D: return tile_flat<T, 2, HamZ2D<T>, STAGE>(P, S, tile);
         case HJR_QUAD_X4D: return tile_flat<T, 4, HamX4D<T>, STAGE>(P, S, tile);
         case HJR_DI2X2: return tile_flat<T, 4, HamDI2X2<T>, STAGE>(P, S, tile);
         default: return 0;
         }
+    } else if constexpr (fam_field(FAM)) {
+        // per-node disturbance boxes: the element tile, both stages
+        constexpr int RS = fam_rs(FAM);
+        if constexpr (fam_x4d(FAM))
+            return tile_plane<T, 4, HamX4DF<T>, STAGE, RS, 2>(P, S, tile, lds);
+        else
+            return tile_plane<T, 2, HamZ2DF<T>, STAGE, RS, 2>(P, S, tile, lds);
     } else {
         constexpr int RS = fam_rs(FAM);
         constexpr int ORDER = fam_order(FAM);

@@ -26,6 +26,7 @@ EXPORTS = (
     "hjr_interp", "hjr_refine_mask", "hjr_solve_levels", "hjr_batch_workspace_bytes",
     "hjr_solve_batch", "hjr_server_create", "hjr_server_submit", "hjr_server_poll",
     "hjr_server_wait", "hjr_server_read_value", "hjr_server_memory", "hjr_server_destroy",
+    "hjr_solve_field",
 )
 
 
@@ -75,7 +76,7 @@ class Problem(C.Structure):
     _fields_ = [("dyn", Dyn), ("nlev", C.c_int32), ("reserved", C.c_int32),
                 ("grids", Grid * 4), ("l", C.c_void_p * 4), ("V", C.c_void_p * 4),
                 ("V0", C.c_void_p), ("d", Dstb * 2), ("tol", C.c_double),
-                ("tile_rows", C.c_int32 * 4), ("band", C.c_double)]
+                ("tile_rows", C.c_int32 * 4), ("band", C.c_double), ("dfield", C.c_void_p * 4)]
 
 
 class ServerCfg(C.Structure):
@@ -88,7 +89,7 @@ class ServerCfg(C.Structure):
 class Request(C.Structure):
     _fields_ = [("instance_id", C.c_uint64), ("dyn", Dyn), ("grid", Grid), ("l", C.c_void_p),
                 ("d", Dstb * 2), ("tol", C.c_double), ("cold", C.c_int32),
-                ("reserved", C.c_int32), ("band", C.c_double)]
+                ("reserved", C.c_int32), ("band", C.c_double), ("dfield", C.c_void_p)]
 
 
 class Reply(C.Structure):
@@ -131,6 +132,9 @@ def lib() -> C.CDLL:
     L.hjr_solve_levels.argtypes = [P(Dyn), C.c_int32, P(Grid), P(C.c_void_p), C.c_void_p,
                                    P(Dstb), C.c_double, P(Opts), P(C.c_void_p), P(C.c_void_p),
                                    P(C.c_int64), P(Stats)]
+    L.hjr_solve_field.restype = st
+    L.hjr_solve_field.argtypes = [P(Dyn), C.c_int32, P(Grid), P(C.c_void_p), P(C.c_void_p),
+                                  C.c_void_p, C.c_double, P(Opts), P(C.c_void_p), P(Stats)]
     L.hjr_batch_workspace_bytes.restype = st
     L.hjr_batch_workspace_bytes.argtypes = [C.c_int32, P(Problem), P(Opts), P(C.c_size_t)]
     L.hjr_solve_batch.restype = st
@@ -235,6 +239,17 @@ def _check_tensor(t, n, dtype, name):
                          f"{t.dtype} {tuple(t.shape)}")
 
 
+def channels(kind: int) -> int:
+    """Disturbance channels of a model (1, or 2 for DI2X2)."""
+    return 2 if kind == DI2X2 else 1
+
+
+def _check_field(f, kind, n, dtype, name):
+    """A per-node disturbance field: device tensor of 2 * channels * N
+    elements (channel, lower/upper, node), contiguous, in the solve dtype."""
+    _check_tensor(f.reshape(-1) if f.is_contiguous() else f, 2 * channels(kind) * n, dtype, name)
+
+
 def _raise(status, what, allow=(OK,)):
     if status not in allow:
         raise HjrError(status, what)
@@ -282,12 +297,15 @@ def tuned(kind, dtype, n):
 
 
 def solve(spec: Spec, l, V0=None, V_out=None, *, dtype=None, order=2, cfl=0.8,
-          max_iter=100000, chunk=None, flags=0, workspace=True, check=True, tile_rows=None):
+          max_iter=100000, chunk=None, flags=0, workspace=True, check=True, tile_rows=None,
+          dfield=None):
     """One safe-set solve.  l, V0, V_out: device tensors of spec.size elements.
-    chunk / tile_rows None take the autotuned values for this shape (library
-    defaults if it was not tuned).  Returns (V_out, stats dict).  Raises
-    HjrError on failure; a solve that hits max_iter returns with
-    stats['status'] == NOT_CONVERGED."""
+    dfield: optional per-node disturbance boxes, a device tensor of
+    (channels, 2, spec.size) elements (hjr_solve_field); without it the
+    constant boxes spec.dlo, spec.dhi apply.  chunk / tile_rows None take
+    the autotuned values for this shape (library defaults if it was not
+    tuned).  Returns (V_out, stats dict).  Raises HjrError on failure; a
+    solve that hits max_iter returns with stats['status'] == NOT_CONVERGED."""
     torch = _torch()
     dtype = dtype or l.dtype
     if chunk is None or tile_rows is None:
@@ -311,11 +329,21 @@ def solve(spec: Spec, l, V0=None, V_out=None, *, dtype=None, order=2, cfl=0.8,
     st = Stats()
     g = make_grid(spec.n, spec.lo, spec.hi)
     dyn = make_dyn(spec.kind, spec.params)
-    d = make_dstb(spec.dlo, spec.dhi)
-    r = lib().hjr_solve_ex(C.byref(dyn), C.byref(g), _ptr(l), _ptr(V0), d, spec.tol,
-                           C.byref(o), _ptr(V_out), C.byref(st))
+    if dfield is not None:
+        _check_field(dfield, spec.kind, N, dtype, "dfield")
+        lp = (C.c_void_p * 1)(l.data_ptr())
+        fp = (C.c_void_p * 1)(dfield.data_ptr())
+        vp = (C.c_void_p * 1)(V_out.data_ptr())
+        r = lib().hjr_solve_field(C.byref(dyn), 1, C.byref(g), lp, fp, _ptr(V0), spec.tol,
+                                  C.byref(o), vp, C.byref(st))
+        what = "hjr_solve_field"
+    else:
+        d = make_dstb(spec.dlo, spec.dhi)
+        r = lib().hjr_solve_ex(C.byref(dyn), C.byref(g), _ptr(l), _ptr(V0), d, spec.tol,
+                               C.byref(o), _ptr(V_out), C.byref(st))
+        what = "hjr_solve_ex"
     if check:
-        _raise(r, "hjr_solve_ex", (OK, NOT_CONVERGED))
+        _raise(r, what, (OK, NOT_CONVERGED))
     del ws
     out = st.as_dict()
     out["return"] = r
@@ -323,10 +351,11 @@ def solve(spec: Spec, l, V0=None, V_out=None, *, dtype=None, order=2, cfl=0.8,
 
 
 def solve_levels(spec: Spec, grids_n, ls, V0=None, *, dtype=None, order=2, cfl=0.8,
-                 max_iter=100000, chunk=0, flags=0, masks=False):
+                 max_iter=100000, chunk=0, flags=0, masks=False, dfields=None):
     """Coarse-to-fine solve: grids_n is a list of per-level node counts over
-    spec's box, ls the per-level constraints.  Returns (list of V per level,
-    list of masks or None, mask counts, stats)."""
+    spec's box, ls the per-level constraints, dfields optional per-level
+    disturbance fields (hjr_solve_field; no masks then).  Returns (list of V
+    per level, list of masks or None, mask counts, stats)."""
     torch = _torch()
     nlev = len(grids_n)
     dtype = dtype or ls[0].dtype
@@ -346,20 +375,31 @@ def solve_levels(spec: Spec, grids_n, ls, V0=None, *, dtype=None, order=2, cfl=0
     o = make_opts(dtype, order, cfl, max_iter, chunk, flags, band=spec.band)
     st = Stats()
     dyn = make_dyn(spec.kind, spec.params)
-    d = make_dstb(spec.dlo, spec.dhi)
-    r = lib().hjr_solve_levels(C.byref(dyn), nlev, grids, lp, _ptr(V0), d, spec.tol,
-                               C.byref(o), vp, mp, counts if masks else None, C.byref(st))
-    _raise(r, "hjr_solve_levels", (OK, NOT_CONVERGED))
+    if dfields is not None:
+        if masks:
+            raise ValueError("hjr_solve_field produces no refinement masks")
+        for k in range(nlev):
+            _check_field(dfields[k], spec.kind, int(np.prod(grids_n[k])), dtype, f"dfields[{k}]")
+        fp = (C.c_void_p * nlev)(*[t.data_ptr() for t in dfields])
+        r = lib().hjr_solve_field(C.byref(dyn), nlev, grids, lp, fp, _ptr(V0), spec.tol,
+                                  C.byref(o), vp, C.byref(st))
+        _raise(r, "hjr_solve_field", (OK, NOT_CONVERGED))
+    else:
+        d = make_dstb(spec.dlo, spec.dhi)
+        r = lib().hjr_solve_levels(C.byref(dyn), nlev, grids, lp, _ptr(V0), d, spec.tol,
+                                   C.byref(o), vp, mp, counts if masks else None, C.byref(st))
+        _raise(r, "hjr_solve_levels", (OK, NOT_CONVERGED))
     out = st.as_dict()
     out["return"] = r
     return Vs, mk, (list(counts) if masks else None), out
 
 
 def make_problem(spec: Spec, l, V_out, V0=None, levels=None, tile_rows=None,
-                 dtype=None) -> Problem:
+                 dtype=None, dfields=None) -> Problem:
     """levels: optional list of (n, l_k, V_k) for a coarse-to-fine job; else
     one level with (spec.n, l, V_out).  tile_rows None takes the autotuned
-    height of every level's shape (dtype: that of the level arrays)."""
+    height of every level's shape (dtype: that of the level arrays).
+    dfields: optional per-level disturbance fields (entries may be None)."""
     p = Problem()
     p.dyn = make_dyn(spec.kind, spec.params)
     if levels is None:
@@ -380,6 +420,11 @@ def make_problem(spec: Spec, l, V_out, V0=None, levels=None, tile_rows=None,
                      for n, lk, _ in levels]
     for k, r in enumerate(tile_rows):
         p.tile_rows[k] = int(r)
+    for k, f in enumerate(dfields or []):
+        if f is not None:
+            n, lk, _ = levels[k]
+            _check_field(f, spec.kind, int(np.prod(n)), lk.dtype, f"dfields[{k}]")
+            p.dfield[k] = f.data_ptr()
     return p
 
 
@@ -459,7 +504,10 @@ class Server:
         _raise(lib().hjr_server_create(C.byref(c), C.byref(h)), "hjr_server_create")
         self._h = h
 
-    def submit(self, instance_id: int, spec: Spec, l_host=None, cold=False) -> int:
+    def submit(self, instance_id: int, spec: Spec, l_host=None, cold=False,
+               dfield_host=None) -> int:
+        """dfield_host: optional per-node disturbance boxes of this request,
+        a host array of (channels, 2, N) values (copied before returning)."""
         req = Request()
         req.instance_id = instance_id
         req.dyn = make_dyn(spec.kind, spec.params)
@@ -468,6 +516,13 @@ class Server:
         if l_host is not None:
             keep = np.ascontiguousarray(l_host, dtype=np.float64 if self.dtype == F64 else np.float32)
             req.l = keep.ctypes.data
+        fkeep = None
+        if dfield_host is not None:
+            fkeep = np.ascontiguousarray(dfield_host,
+                                         dtype=np.float64 if self.dtype == F64 else np.float32)
+            if fkeep.size != 2 * channels(spec.kind) * spec.size:
+                raise ValueError("dfield_host must hold (channels, 2, N) values")
+            req.dfield = fkeep.ctypes.data
         dd = make_dstb(spec.dlo, spec.dhi)
         req.d[0] = dd[0]
         req.d[1] = dd[1]

@@ -42,8 +42,9 @@ int main(void){
  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hjr_grid), sizeof(hjr_dyn),
    sizeof(hjr_dstb), sizeof(hjr_opts), sizeof(hjr_stats), sizeof(hjr_problem),
    sizeof(hjr_server_cfg), sizeof(hjr_request), sizeof(hjr_reply));
- printf("%zu %zu %zu %zu\n", offsetof(hjr_opts, flags), offsetof(hjr_stats, kernel_launches),
-   offsetof(hjr_problem, tol), offsetof(hjr_request, cold));
+ printf("%zu %zu %zu %zu %zu %zu\n", offsetof(hjr_opts, flags),
+   offsetof(hjr_stats, kernel_launches), offsetof(hjr_problem, tol), offsetof(hjr_request, cold),
+   offsetof(hjr_problem, dfield), offsetof(hjr_request, dfield));
  return 0; }
 """
     with tempfile.TemporaryDirectory() as d:
@@ -57,7 +58,7 @@ int main(void){
             C.sizeof(hjr.Stats), C.sizeof(hjr.Problem), C.sizeof(hjr.ServerCfg),
             C.sizeof(hjr.Request), C.sizeof(hjr.Reply),
             hjr.Opts.flags.offset, hjr.Stats.kernel_launches.offset, hjr.Problem.tol.offset,
-            hjr.Request.cold.offset]
+            hjr.Request.cold.offset, hjr.Problem.dfield.offset, hjr.Request.dfield.offset]
     assert got == want
 
 
@@ -156,6 +157,26 @@ def test_interp_and_mask_reject_invalid():
     assert L.hjr_interp(C.byref(a), p, C.byref(a), p, None, None) == hjr.EINVAL  # aliasing
     bad = hjr.make_grid((1, 11), (0, 0), (1, 1))
     assert L.hjr_refine_mask(C.byref(bad), p, q, None, None) == hjr.EINVAL
+
+
+def test_field_solve_rejects_invalid_without_device():
+    L = hjr.lib()
+    dyn = hjr.make_dyn(hjr.QUAD_Z2D, (0.91, 9.81, 7.0, 16.0))
+    g = (hjr.Grid * 1)(hjr.make_grid((11, 11), (0, -4), (3, 4)))
+    p = (C.c_void_p * 1)(0x1000)
+    q = (C.c_void_p * 1)(0x2000)
+    none = (C.c_void_p * 1)(None)
+    o = hjr.Opts()
+    L.hjr_opts_default(C.byref(o))
+    # missing field array, a missing level field, level counts out of range
+    assert L.hjr_solve_field(C.byref(dyn), 1, g, p, None, None, 1e-4, C.byref(o), q, None) == hjr.EINVAL
+    assert L.hjr_solve_field(C.byref(dyn), 1, g, p, none, None, 1e-4, C.byref(o), q, None) == hjr.EINVAL
+    assert L.hjr_solve_field(C.byref(dyn), 0, g, p, p, None, 1e-4, C.byref(o), q, None) == hjr.EINVAL
+    assert L.hjr_solve_field(C.byref(dyn), 5, g, p, p, None, 1e-4, C.byref(o), q, None) == hjr.EINVAL
+    # the usual argument checks apply (tol, grid) before any device work
+    assert L.hjr_solve_field(C.byref(dyn), 1, g, p, p, None, 0.0, C.byref(o), q, None) == hjr.EINVAL
+    bad = (hjr.Grid * 1)(hjr.make_grid((2, 11), (0, -4), (3, 4)))
+    assert L.hjr_solve_field(C.byref(dyn), 1, bad, p, p, None, 1e-4, C.byref(o), q, None) == hjr.EINVAL
 
 
 def test_batch_and_server_reject_invalid():
