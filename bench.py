@@ -19,7 +19,9 @@ CPU.
 Other modes (not the headline line): --mode batch (256 seeded subsystem
 solves, plain one-solve-per-call vs batched), --mode serve (Poisson request
 stream through the continuous-batching server), --mode warm (warm start and
-coarse-to-fine vs cold on the 4-D x-subsystem).
+coarse-to-fine vs cold on the 4-D x-subsystem), --mode field (the same
+decomposed solve with state-dependent disturbance bounds, a per-node
+interval on every grid level, and the roofline of its stage-2 kernel).
 """
 from __future__ import annotations
 
@@ -42,7 +44,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "warm", "copy", "precision", "kernels"])
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "warm", "copy", "precision", "kernels",
+                             "field", "field_kernels"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk", type=int, default=None, help="RK2 steps per chunk (default: autotuned)")
@@ -196,6 +199,160 @@ def mode_step(args, torch, hjr, W):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, W)
     return out
+
+
+# ---------------------------------------------------------------------------
+# field mode: state-dependent disturbance bounds (d in D(x), a GP-shaped
+# interval per node) on every level of the decomposed solve
+# ---------------------------------------------------------------------------
+
+def field_of(W, kind, n):
+    return W.wind_x4d(n) if kind == W.QUAD_X4D else W.wind_z2d(n)
+
+
+def build_field_step(torch, hjr, W):
+    """(name, spec, levels, fields) per subsystem: x, y on 21^4 -> 41^4 with
+    the 4-D update band, z on 51^2 -> 101^2, each level with its own field."""
+    subs = [("x", W.quad_x4d, [21, 41]), ("y", W.quad_x4d, [21, 41]), ("z", W.quad_z2d, [51, 101])]
+    jobs = []
+    for name, mk, ns in subs:
+        lv, fs = [], []
+        for n in ns:
+            P = mk(n, 0.5, name)
+            l = torch.tensor(P.l, dtype=torch.float32, device="cuda")
+            lv.append((P.n, l, torch.empty_like(l)))
+            fs.append(torch.tensor(field_of(W, P.kind, n), dtype=torch.float32, device="cuda"))
+        P = mk(ns[-1], 0.5, name)
+        if P.kind == W.QUAD_X4D:
+            P.band = W.BAND_4D_UPDATE
+        jobs.append((name, hjr.Spec.of(P), lv, fs))
+    return jobs
+
+
+def field_cpu_baseline(seconds, W):
+    """The oracle on a bounded sample of the field workload: RK2 steps of
+    the 41^4 x-subsystem with its per-node bounds, single thread."""
+    from oracle import oracle as O
+    P = W.quad_x4d(41, 0.5)
+    f = W.wind_x4d(41)
+    g = O.make_grid(P.n, P.lo, P.hi)
+    d = O.make_dyn(P.kind, P.params)
+    alpha = O.lf_alpha(d, g, None, None, dfield=f)
+    dt = O.dt(g, alpha)
+    V = P.l.copy()
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        V, _ = O.iterate(d, g, None, None, alpha, dt, P.l, V, dfield=f)
+        steps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    return dict(value=P.size * steps / el, unit="cell-updates/s", cores=1, kind="oracle",
+                sample=f"{steps} RK2 steps of the 41^4 x-subsystem with per-node bounds "
+                       f"(FP64 oracle, 1 thread, {el:.1f} s)")
+
+
+def field_x4d_problems(torch, hjr, W):
+    Ps = [W.quad_x4d(41, 0.5, "x"), W.quad_x4d(41, 0.5, "y")]
+    ls = [torch.tensor(P.l, dtype=torch.float32, device="cuda") for P in Ps]
+    fs = [torch.tensor(W.wind_x4d(41), dtype=torch.float32, device="cuda") for _ in Ps]
+    Vs = [torch.empty_like(l) for l in ls]
+    keep = (ls, fs, Vs)
+    return [hjr.make_problem(hjr.Spec.of(P), l, V, dfields=[f])
+            for P, l, V, f in zip(Ps, ls, Vs, fs)], keep
+
+
+def mode_field(args, torch, hjr, W):
+    jobs = build_field_step(torch, hjr, W)
+
+    def run():
+        probs = [hjr.make_problem(spec, None, None, levels=lv, dfields=fs)
+                 for _, spec, lv, fs in jobs]
+        return hjr.solve_batch(probs, dtype=torch.float32, chunk=args.chunk)
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    lat, cu, it_levels, status = [], 0, None, None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        r, stats = run()
+        lat.append((time.perf_counter() - s0) * 1e3)
+        status = [s["status"] for s in stats]
+        cu += sum(s["cell_updates"] for s in stats)
+        it_levels = {name: s["level_iterations"][: len(lv)]
+                     for (name, _, lv, _), s in zip(jobs, stats)}
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # stage-2 kernel of the 4-D field family: reads Vhat, V, l and the two
+    # bounds, writes V (6 x 4 B per cell-update); stage 1 reads V and the
+    # bounds and writes Vhat (16 B)
+    probs, keep = field_x4d_problems(torch, hjr, W)
+    hjr.solve_batch(probs, dtype=torch.float32, max_iter=32, chunk=args.chunk)
+    _, st = hjr.solve_batch(probs, dtype=torch.float32, max_iter=512, chunk=args.chunk,
+                            flags=hjr.FLAG_PROFILE)
+    kms = np.asarray(st[0]["kernel_ms"])
+    kn = np.asarray(st[0]["kernel_launches"])
+    kcu = st[0]["kernel_cell_updates"]
+    achieved = kcu * 24.0 / (kms[1] * 1e-3) / 1e9
+    out = {
+        "metric": "grid cell-updates/s",
+        "value": cu / el,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "decomposed 10-D near-hover quadcopter with state-dependent disturbance "
+                        "bounds (GP-shaped mean -/+ 3 sigma per node): x,y 4-D 21^4 -> 41^4 "
+                        "(residual band 0.5) + z 2-D 51^2 -> 101^2, FP32 values / FP64 "
+                        "residual, ENO2+LF+TVD-RK2, CFL 0.8, tol 1e-4, 3 subsystems in one "
+                        "batched solve",
+            "cell_updates_per_step": cu / args.steps,
+            "iterations_per_level": it_levels,
+            "status": status,
+        },
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_stage<float,2,X4D narrow, per-node bounds> (RK stage 2 + projection + "
+                      "residual), x,y 41^4 batched",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic("field_stage2"),
+            "bytes_per_cell_update": 24,
+            "avg_launch_us": kms[1] / max(kn[1], 1) * 1e3,
+            "launches_timed": int(kn[1]),
+            "cell_updates_timed": int(kcu),
+            "stage1_plus_stage2_GBs": kcu * 40.0 / ((kms[0] + kms[1]) * 1e-3) / 1e9,
+        },
+    }
+    del keep
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = field_cpu_baseline(args.cpu_seconds, W)
+    return out
+
+
+def mode_field_kernels(args, torch, hjr, W):
+    """64 RK2 steps of the field workload's x, y on 41^4, launched kernel by
+    kernel, for counter collection."""
+    probs, keep = field_x4d_problems(torch, hjr, W)
+    _, st = hjr.solve_batch(probs, dtype=torch.float32, max_iter=64, chunk=16,
+                            flags=hjr.FLAG_NO_GRAPH | hjr.FLAG_NO_PIPELINE)
+    torch.cuda.synchronize()
+    del keep
+    return {"mode": "field_kernels", "workload": "x, y 41^4 FP32 with per-node bounds, batched, "
+            "64 RK2 steps", "iterations": st[0]["iterations"]}
 
 
 # ---------------------------------------------------------------------------
@@ -466,7 +623,8 @@ def main():
         sys.exit(2)
     hjr.lib()
     fn = {"step": mode_step, "batch": mode_batch, "serve": mode_serve, "warm": mode_warm,
-          "copy": mode_copy, "precision": mode_precision, "kernels": mode_kernels}[args.mode]
+          "copy": mode_copy, "precision": mode_precision, "kernels": mode_kernels,
+          "field": mode_field, "field_kernels": mode_field_kernels}[args.mode]
     out = fn(args, torch, hjr, W)
     print(json.dumps(out), flush=True)
 

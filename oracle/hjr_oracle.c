@@ -649,3 +649,94 @@ int64_t orc_refine_mask(const orc_grid* g, const double* V, uint8_t* mask)
     }
     return count;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Safety query: value, gradient and optimal safety control at a state      */
+/* ------------------------------------------------------------------------ */
+
+/* Gradient the scheme evaluates H with at node idx: per axis the mean of
+ * the one-sided ENO derivatives, (p+_i + p-_i) / 2. */
+static void node_pbar(const orc_grid* g, const double* V, int order, int64_t idx,
+                      double* pbar)
+{
+    int D = g->ndim;
+    int j[4];
+    double w[5];
+    unflatten(g, idx, j);
+    for (int i = 0; i < D; i++) {
+        int64_t s = stride_of(g, i);
+        const double* line0 = V + (idx - (int64_t)j[i] * s);
+        for (int k = 0; k < 5; k++) w[k] = line_value(line0, s, g->n[i], j[i] - 2 + k);
+        double pm, pp;
+        eno_point(w, spacing(g, i), order, &pm, &pp);
+        pbar[i] = 0.5 * (pp + pm);
+    }
+}
+
+int orc_query(const orc_dyn* dyn, const orc_grid* g, const double* V, int order,
+              const double* dlo, const double* dhi, const double* x,
+              double* value, double* grad, double* u_star)
+{
+    int D = g->ndim;
+    int mu = orc_num_ctrl(dyn->kind), md = orc_num_dstb(dyn->kind);
+    int j0[4];
+    double t[4];
+    int inside = 1;
+    for (int i = 0; i < D; i++) {
+        if (!(x[i] >= g->lo[i] && x[i] <= g->hi[i])) inside = 0;
+    }
+    if (!inside) {
+        *value = NAN;
+        for (int i = 0; i < D; i++) grad[i] = NAN;
+        for (int k = 0; k < mu; k++) u_star[k] = NAN;
+        return ORC_EINVAL;
+    }
+    /* the cell holding x: node j0 and fractions t along each axis */
+    for (int i = 0; i < D; i++) {
+        double s = (x[i] - g->lo[i]) / spacing(g, i);
+        int j = (int)floor(s);
+        if (j < 0) j = 0;
+        if (j > g->n[i] - 2) j = g->n[i] - 2;
+        j0[i] = j;
+        t[i] = s - (double)j;
+    }
+    /* multilinear interpolation of V and of the node gradients over the
+     * 2^D corners, in row-major order of the corner offsets */
+    double v = 0.0, gr[4] = {0.0, 0.0, 0.0, 0.0}, pb[4];
+    for (int c = 0; c < (1 << D); c++) {
+        double wgt = 1.0;
+        int64_t idx = 0;
+        for (int i = 0; i < D; i++) {
+            int o = (c >> (D - 1 - i)) & 1;
+            wgt *= o ? t[i] : 1.0 - t[i];
+            idx += (int64_t)(j0[i] + o) * stride_of(g, i);
+        }
+        v += wgt * V[idx];
+        node_pbar(g, V, order, idx, pb);
+        for (int i = 0; i < D; i++) gr[i] += wgt * pb[i];
+    }
+    *value = v;
+    for (int i = 0; i < D; i++) grad[i] = gr[i];
+    /* u* = a control vertex maximising min over d of grad . f(x, u, d);
+     * of equal candidates the later vertex in enumeration order is kept,
+     * which is the upper bound of every input that does not matter */
+    double ulo[4], uhi[4], u[4], d[4], f[4];
+    orc_ctrl_box(dyn, ulo, uhi);
+    double best = -INFINITY;
+    for (int vu = 0; vu < (1 << mu); vu++) {
+        box_vertex(mu, ulo, uhi, vu, u);
+        double worst = INFINITY;
+        for (int vd = 0; vd < (1 << md); vd++) {
+            box_vertex(md, dlo, dhi, vd, d);
+            orc_dynamics(dyn, x, u, d, f);
+            double sum = 0.0;
+            for (int i = 0; i < D; i++) sum += gr[i] * f[i];
+            if (sum < worst) worst = sum;
+        }
+        if (worst >= best) {
+            best = worst;
+            for (int k = 0; k < mu; k++) u_star[k] = u[k];
+        }
+    }
+    return ORC_OK;
+}

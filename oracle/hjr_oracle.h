@@ -187,6 +187,20 @@ int orc_solve_field(const orc_dyn* dyn, const orc_grid* g, const double* l,
                     int64_t* iterations, double* residual, double* dt_out,
                     double* alpha_out, double* res_hist, double* max_rise);
 
+/* Safety query at the state x (Sec. II-A: the gradient of the converged
+ * value gives the optimal safety control, the optimiser of the
+ * Hamiltonian).  value: multilinear interpolation of V at x (corner
+ * weights products of t and 1 - t, t the fraction of x in its cell, corners
+ * summed in row-major order of their offsets); grad: the same interpolation
+ * of the node gradients (p+_i + p-_i)/2 of the scheme (order 2 = ENO2);
+ * u_star: a vertex of the control box maximising min over the disturbance
+ * box [dlo, dhi] of grad . f(x, u, d), by enumeration; among equal vertices
+ * the upper bound of an input is taken.  Returns ORC_OK, or ORC_EINVAL with
+ * NaN outputs when x lies outside the grid box. */
+int orc_query(const orc_dyn* dyn, const orc_grid* g, const double* V, int order,
+              const double* dlo, const double* dhi, const double* x,
+              double* value, double* grad, double* u_star);
+
 #ifdef __cplusplus
 }
 #endif

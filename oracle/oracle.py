@@ -94,6 +94,8 @@ def lib():
         L.orc_iterate_at_field.restype = C.c_double
         L.orc_iterate_at_field.argtypes = [yp, gp, dp, dp, dp, dp, C.c_double, C.c_int, dp,
                                            dp, C.c_int64]
+        L.orc_query.restype = C.c_int
+        L.orc_query.argtypes = [yp, gp, dp, C.c_int, dp, dp, dp, dp, dp, dp]
         L.orc_solve_field.restype = C.c_int
         L.orc_solve_field.argtypes = [yp, gp, dp, dp, dp, dp, dp, C.c_double, C.c_double,
                                       C.c_double, C.c_int, C.c_int64, dp,
@@ -280,3 +282,28 @@ def refine_mask(grid: Grid, V):
     cnt = lib().orc_refine_mask(C.byref(grid), _dp(V),
                                 m.ctypes.data_as(C.POINTER(C.c_uint8)))
     return m, int(cnt)
+
+
+def query(dyn: Dyn, grid: Grid, V, X, dlo, dhi, order=2):
+    """Safety query at every row of X (states, shape (n, ndim)): returns
+    dict(value (n,), grad (n, ndim), u (n, controls), ok (n,) bool)."""
+    V = _f64(V)
+    X = np.atleast_2d(_f64(X))
+    lo, hi = _dbounds(dlo, dhi)
+    D = grid.ndim
+    m = 2 if dyn.kind == DI2X2 else 1
+    n = X.shape[0]
+    val = np.zeros(n)
+    grad = np.zeros((n, D))
+    u = np.zeros((n, m))
+    ok = np.zeros(n, dtype=bool)
+    xb, gb, ub, vb = np.zeros(4), np.zeros(4), np.zeros(4), C.c_double(0)
+    for i in range(n):
+        xb[:D] = X[i]
+        st = lib().orc_query(C.byref(dyn), C.byref(grid), _dp(V), int(order), _dp(lo), _dp(hi),
+                             _dp(xb), C.byref(vb), _dp(gb), _dp(ub))
+        val[i] = vb.value
+        grad[i] = gb[:D]
+        u[i] = ub[:m]
+        ok[i] = st == OK
+    return dict(value=val, grad=grad, u=u, ok=ok)

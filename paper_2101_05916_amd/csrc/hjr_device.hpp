@@ -23,15 +23,6 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #ifndef HJR_NODE_UNROLL
 #define HJR_NODE_UNROLL 2            // nodes of a lane whose loads are issued together
 #endif
-#ifndef HJR_PLANE_QUAD1
-#define HJR_PLANE_QUAD1 0            // stage 1 plane tiles with 16-byte accesses (four nodes per lane)
-#endif
-#ifndef HJR_PLANE_QUAD2
-#define HJR_PLANE_QUAD2 1            // the same for stage 2
-#endif
-#ifndef HJR_HOIST_LOADS
-#define HJR_HOIST_LOADS 1            // issue a tile's first node loads before building its LDS block
-#endif
 #ifndef HJR_BLOCKS_PER_CU
 #define HJR_BLOCKS_PER_CU 24         // cap on stage workgroups per CU (6 single-wave groups per SIMD)
 #endif

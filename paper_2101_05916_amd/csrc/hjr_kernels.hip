@@ -122,7 +122,9 @@ __device__ __forceinline__ void flush_residual(const ChunkArgs& A, int p, uint64
 template <typename T, int STAGE, int FAM>
 __global__ __launch_bounds__(kStageBlock) HJR_STAGE_ATTR void k_stage(ChunkArgs A)
 {
-    constexpr int kElems = FAM == kFamFlat ? 4 : plane_elems(fam_rs(FAM)) + kStageBlock + 16;
+    // a plane block and one spare slot per lane (lanes past the end of a
+    // tile stage into their spare slot)
+    constexpr int kElems = FAM == kFamFlat ? 4 : plane_elems(fam_rs(FAM)) + kStageBlock;
     __shared__ uint64_t red[kStageBlock / 64];
     __shared__ __align__(16) char smem[kElems * sizeof(T)];
     T* lds = (T*)smem;

@@ -65,55 +65,6 @@ __device__ __forceinline__ void st64(T* base, int64_t i, T v)
     ((HJR_GLOBAL T*)base)[i] = v;
 }
 
-// Four consecutive elements through the global address space: one 16-byte
-// access per 4 floats or 2 doubles.  Plain global accesses need only 4-byte
-// alignment here (the vector types below say so); base is uniform (an SGPR
-// pair) and byte_off a 32-bit VGPR offset.
-typedef float hjr_f4u __attribute__((ext_vector_type(4), aligned(4)));
-typedef double hjr_d2u __attribute__((ext_vector_type(2), aligned(8)));
-
-template <typename T>
-__device__ __forceinline__ void gld4(T* v, const T* base, uint32_t byte_off)
-{
-    const HJR_GLOBAL char* p = (const HJR_GLOBAL char*)base + byte_off;
-    if constexpr (sizeof(T) == 4) {
-        const hjr_f4u a = *(const HJR_GLOBAL hjr_f4u*)p;
-        v[0] = a.x;
-        v[1] = a.y;
-        v[2] = a.z;
-        v[3] = a.w;
-    } else {
-        const hjr_d2u a = *(const HJR_GLOBAL hjr_d2u*)p;
-        const hjr_d2u b = *(const HJR_GLOBAL hjr_d2u*)(p + 16);
-        v[0] = a.x;
-        v[1] = a.y;
-        v[2] = b.x;
-        v[3] = b.y;
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void gst4(const T* v, T* base, uint32_t byte_off)
-{
-    HJR_GLOBAL char* p = (HJR_GLOBAL char*)base + byte_off;
-    if constexpr (sizeof(T) == 4) {
-        hjr_f4u a;
-        a.x = v[0];
-        a.y = v[1];
-        a.z = v[2];
-        a.w = v[3];
-        *(HJR_GLOBAL hjr_f4u*)p = a;
-    } else {
-        hjr_d2u a, b;
-        a.x = v[0];
-        a.y = v[1];
-        b.x = v[2];
-        b.y = v[3];
-        *(HJR_GLOBAL hjr_d2u*)p = a;
-        *(HJR_GLOBAL hjr_d2u*)(p + 16) = b;
-    }
-}
-
 template <typename T>
 __device__ __forceinline__ T gld1(const T* base, uint32_t byte_off)
 {
@@ -223,7 +174,6 @@ struct HamZ2D {
     }
     // per-node data: none (no per-row table)
     typedef T Node;
-    __device__ __forceinline__ T row_coef(int) const { return T(0); }
     __device__ __forceinline__ Node node_b(int, uint32_t) const { return T(0); }
     __device__ __forceinline__ Node node_i(int, int64_t) const { return T(0); }
     __device__ __forceinline__ T eval(const T* sum, int j0, int j1, int j2, int j3, T) const
@@ -725,197 +675,6 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
     return rmax;
 }
 
-// The same tile with every global access 16 bytes wide: lane t owns the
-// four consecutive nodes 4t .. 4t+3 of each group of 4 x kStageBlock nodes,
-// so the eight outer-axis neighbours, V and l of a quad are eight (ten)
-// 16-byte loads and its result one 16-byte store, and the staged rows are
-// loaded the same way.  A quad cut by the end of the tile falls back to
-// element accesses with clamped indices (at most one lane per tile); lanes
-// past the end skip their accesses.  The per-row table of the Hamiltonian
-// is staged in LDS after the block.
-template <typename T, int D, class Ham, int STAGE, int RS, int ORDER>
-__device__ uint64_t tile_plane_q(PDesc& P, PState& S, uint32_t tile, T* lds)
-{
-    constexpr int kSpare = plane_elems(RS);
-    constexpr int kTab = kSpare + kStageBlock;  // LDS offset of the row table
-    constexpr int kNodeQ = kPlaneNodesPT / 4;   // node quads per lane
-    const T* __restrict__ in = (const T*)(STAGE == 1 ? P.V : P.Vhat);
-    const int ra = D - 2, ca = D - 1;  // row axis, column axis
-    const int nr = P.n[ra], nc = P.n[ca];
-    const uint32_t outer = P.chunks == 1 ? tile : fdiv(tile, P.div_chunks);
-    const int chunk = (int)(tile - outer * (uint32_t)P.chunks);
-    int i0 = 0, i1 = 0;
-    if (D == 4) {
-        i0 = (int)fdiv(outer, P.div[1]);
-        i1 = (int)outer - i0 * P.n[1];
-    }
-    const int r0 = chunk * P.rows;
-    const int r1 = min(r0 + P.rows, nr);
-    const uint32_t plane0 = outer * (uint32_t)(nr * nc);
-    const int lr0 = max(r0 - 2, 0), lr1 = min(r1 + 2, nr);
-    const uint32_t load0 = plane0 + (uint32_t)(lr0 * nc);  // the loaded rows are contiguous
-    const int lrow = lr0 - r0 + 2;                         // LDS row of the first loaded row
-    const int cnt = (r1 - r0) * nc;
-    const uint32_t node0 = plane0 + (uint32_t)(r0 * nc);
-    const int tid = threadIdx.x;
-    constexpr uint32_t B = sizeof(T);
-    Ham ham;
-    ham.init(P);
-
-    if (D == 4 && tid < r1 - r0) lds[kTab + tid] = ham.row_coef(r0 + tid);
-    // outer-axis neighbours: one uniform base pointer per neighbour, shared
-    // by every node of the tile, and the node's byte offset in a VGPR
-    int o0[4] = {0, 0, 0, 0}, o1[4] = {0, 0, 0, 0};
-    if (D == 4) {
-        clamped_offsets(i0, P.n[0], (int)P.stride[0], o0);
-        clamped_offsets(i1, P.n[1], (int)P.stride[1], o1);
-    }
-    const T* nb[8];
-#pragma unroll
-    for (int qq = 0; qq < 4; qq++) {
-        nb[qq] = in + o0[qq];
-        nb[4 + qq] = in + o1[qq];
-    }
-    T* const vout = (T*)(STAGE == 1 ? P.Vhat : P.V);
-    const T* const lc = (const T*)P.l;
-    // the global loads of node group g (neighbours, and V, l in stage 2)
-    auto load_group = [&](int g, T (&w)[8][4], T (&vo)[4], T (&lv)[4]) {
-        const int q0 = 4 * (tid + g * kStageBlock);
-        const bool full = q0 + 3 < cnt, any = q0 < cnt;
-        const uint32_t vb = (node0 + (uint32_t)q0) * B;
-        if (full) {
-            if (D == 4) {
-#pragma unroll
-                for (int qq = 0; qq < 8; qq++) gld4<T>(w[qq], nb[qq], vb);
-            }
-            if (STAGE == 2) {
-                gld4<T>(vo, vout, vb);
-                gld4<T>(lv, lc, vb);
-            }
-        } else if (any) {
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const uint32_t vj = (node0 + (uint32_t)min(q0 + j, cnt - 1)) * B;
-                if (D == 4) {
-#pragma unroll
-                    for (int qq = 0; qq < 8; qq++) w[qq][j] = gld1<T>(nb[qq], vj);
-                }
-                if (STAGE == 2) {
-                    vo[j] = gld1<T>(vout, vj);
-                    lv[j] = gld1<T>(lc, vj);
-                }
-            }
-        }
-    };
-    // group 0's loads go out now, so that their latency overlaps the
-    // building of the LDS block (they do not read LDS)
-    T w0[8][4], vo0[4], lv0[4];
-    if (HJR_HOIST_LOADS) load_group(0, w0, vo0, lv0);
-
-    // ---- LDS block: loaded rows, then ghost columns and ghost rows ----
-    stage_flat<T, RS>(in, load0, nc, lr1 - lr0, lrow, lds, tid, P.div_last);
-    __syncthreads();
-    const int nghc = (lr1 - lr0) * 4;
-    for (int e = tid; e < nghc; e += kStageBlock) {
-        // column -1 - s (left) or nc + s (right), s = 0, 1, of loaded row e/4
-        T* row = lds + (lrow + (e >> 2)) * RS + 2;
-        const bool right = (e & 2) != 0, far = (e & 1) != 0;
-        const T v0 = row[right ? nc - 1 : 0], v1 = row[right ? nc - 2 : 1];
-        row[right ? nc + (e & 1) : -1 - (e & 1)] = far ? T(3) * v0 - T(2) * v1 : T(2) * v0 - v1;
-    }
-    const bool glo = (r0 - 2 < 0), ghi = (r1 + 2 > nr);
-    if (glo || ghi) {
-        for (int e = tid; e < 2 * nc; e += kStageBlock) {
-            const int k = e >= nc ? 1 : 0, cc = e - k * nc;
-            if (glo) {
-                const T v0 = lds[(2 - r0) * RS + cc + 2], v1 = lds[(3 - r0) * RS + cc + 2];
-                const int r = k == 0 ? -1 : -2;
-                if (r >= r0 - 2)
-                    lds[(r - r0 + 2) * RS + cc + 2] = k == 0 ? T(2) * v0 - v1 : T(3) * v0 - T(2) * v1;
-            }
-            if (ghi) {
-                const T v0 = lds[(nr + 1 - r0) * RS + cc + 2], v1 = lds[(nr - r0) * RS + cc + 2];
-                const int r = k == 0 ? nr : nr + 1;
-                if (r <= r1 + 1)
-                    lds[(r - r0 + 2) * RS + cc + 2] = k == 0 ? T(2) * v0 - v1 : T(3) * v0 - T(2) * v1;
-            }
-        }
-    }
-    __syncthreads();
-
-    // ---- stencil, one quad of nodes per lane and group ----
-    T ah[4];
-#pragma unroll
-    for (int a = 0; a < 4; a++) ah[a] = Prec<T>::ah(S)[a];
-    const T dt = Prec<T>::dt(S);
-    const bool edge0 = D == 4 && (i0 < 2 || i0 > P.n[0] - 3);
-    const bool edge1 = D == 4 && (i1 < 2 || i1 > P.n[1] - 3);
-    uint64_t rmax = 0;
-    // stencil of node group g from its loaded values; stores the results
-    auto compute_group = [&](int g, T (&w)[8][4], T (&vo)[4], T (&lv)[4]) {
-            const int q0 = 4 * (tid + g * kStageBlock);  // first node of this lane's quad
-            const bool full = q0 + 3 < cnt, any = q0 < cnt;
-            const uint32_t vb = (node0 + (uint32_t)q0) * B;
-            T out[4];
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const bool live = q0 + j < cnt;
-                const int e = min(q0 + j, cnt - 1);  // lanes past the end read valid LDS
-                const int rr = (int)fdiv((uint32_t)e, P.div_last);
-                const int cc = e - rr * nc;
-                const T* q = lds + (rr + 2) * RS + cc + 2;
-                const T c = q[0];
-                T sum[4], dif;
-                eno_sd<T, ORDER>(q[-2 * RS], q[-RS], c, q[RS], q[2 * RS], sum[ra], dif);
-                T L = ah[ra] * dif;
-                eno_sd<T, ORDER>(q[-2], q[-1], c, q[1], q[2], sum[ca], dif);
-                L += ah[ca] * dif;
-                if (D == 4) {
-                    T m2 = w[0][j], m1 = w[1][j], p1 = w[2][j], p2 = w[3][j];
-                    if (edge0) ghost_fix<T>(i0, P.n[0], c, m2, m1, p1, p2);
-                    eno_sd<T, ORDER>(m2, m1, c, p1, p2, sum[0], dif);
-                    L += ah[0] * dif;
-                    m2 = w[4][j];
-                    m1 = w[5][j];
-                    p1 = w[6][j];
-                    p2 = w[7][j];
-                    if (edge1) ghost_fix<T>(i1, P.n[1], c, m2, m1, p1, p2);
-                    eno_sd<T, ORDER>(m2, m1, c, p1, p2, sum[1], dif);
-                    L += ah[1] * dif;
-                    L += ham.eval(sum, i0, i1, r0 + rr, cc, lds[kTab + rr]);
-                } else {
-                    L += ham.eval(sum, r0 + rr, cc, 0, 0, T(0));
-                }
-                if (STAGE == 1) {
-                    out[j] = c + dt * L;
-                } else {
-                    const T vt = c + dt * L;
-                    const T avg = T(0.5) * (vo[j] + vt);
-                    const T vn = (lv[j] < avg) ? lv[j] : avg;
-                    out[j] = vn;
-                    const uint64_t r = dbits(fabs((double)vn - (double)vo[j]));
-                    if (live && in_band(vn, vo[j], P.band)) rmax = umax64(rmax, r);
-                }
-            }
-            if (full) {
-                gst4<T>(out, vout, vb);
-            } else if (any) {
-#pragma unroll
-                for (int j = 0; j < 4; j++)
-                    if (q0 + j < cnt) gst1<T>(out[j], vout, (node0 + (uint32_t)(q0 + j)) * B);
-            }
-    };
-    static_assert(kNodeQ == 2, "two node groups per lane and tile");
-    T w1[8][4], vo1[4], lv1[4];
-    if (!HJR_HOIST_LOADS) load_group(0, w0, vo0, lv0);
-    const bool two = 4 * kStageBlock < cnt;  // uniform: group 1 has nodes
-    if (two) load_group(1, w1, vo1, lv1);
-    compute_group(0, w0, vo0, lv0);
-    if (two) compute_group(1, w1, vo1, lv1);
-    __syncthreads();  // the LDS block is reused by the next tile
-    return rmax;
-}
-
 // One tile of a family (see Family): flat tiles dispatch on the model (and
 // on whether the problem has a disturbance field) at run time, plane
 // families are fixed at compile time.
@@ -948,22 +707,10 @@ __device__ __forceinline__ uint64_t run_tile(PDesc& P, PState& S, uint32_t tile,
     } else {
         constexpr int RS = fam_rs(FAM);
         constexpr int ORDER = fam_order(FAM);
-        // FP32 stage 2 (five arrays per node) runs the 16-byte tile; stage 1
-        // and FP64 run the element tile (the faster choices on gfx950; the
-        // FP64 16-byte tile needs too many registers)
-        constexpr bool quad = STAGE == 1 ? HJR_PLANE_QUAD1 != 0
-                                         : (HJR_PLANE_QUAD2 != 0 && sizeof(T) == 4);
-        if constexpr (quad) {
-            if constexpr (fam_x4d(FAM))
-                return tile_plane_q<T, 4, HamX4D<T>, STAGE, RS, ORDER>(P, S, tile, lds);
-            else
-                return tile_plane_q<T, 2, HamZ2D<T>, STAGE, RS, ORDER>(P, S, tile, lds);
-        } else {
-            if constexpr (fam_x4d(FAM))
-                return tile_plane<T, 4, HamX4D<T>, STAGE, RS, ORDER>(P, S, tile, lds);
-            else
-                return tile_plane<T, 2, HamZ2D<T>, STAGE, RS, ORDER>(P, S, tile, lds);
-        }
+        if constexpr (fam_x4d(FAM))
+            return tile_plane<T, 4, HamX4D<T>, STAGE, RS, ORDER>(P, S, tile, lds);
+        else
+            return tile_plane<T, 2, HamZ2D<T>, STAGE, RS, ORDER>(P, S, tile, lds);
     }
 }
 
