@@ -21,7 +21,9 @@ solves, plain one-solve-per-call vs batched), --mode serve (Poisson request
 stream through the continuous-batching server), --mode warm (warm start and
 coarse-to-fine vs cold on the 4-D x-subsystem), --mode field (the same
 decomposed solve with state-dependent disturbance bounds, a per-node
-interval on every grid level, and the roofline of its stage-2 kernel).
+interval on every grid level, and the roofline of its stage-2 kernel),
+--mode query (safety queries -- value, gradient, optimal control, filter --
+on the converged 41^4 x-subsystem: latency per call and queries/s).
 """
 from __future__ import annotations
 
@@ -45,7 +47,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "warm", "copy", "precision", "kernels",
-                             "field", "field_kernels"])
+                             "field", "field_kernels", "query"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk", type=int, default=None, help="RK2 steps per chunk (default: autotuned)")
@@ -356,6 +358,72 @@ def mode_field_kernels(args, torch, hjr, W):
 
 
 # ---------------------------------------------------------------------------
+# query mode: safety queries on a converged value function
+# ---------------------------------------------------------------------------
+
+def mode_query(args, torch, hjr, W):
+    """The 41^4 x-subsystem solved cold on the device (FP32), then safety
+    queries (value, gradient, u*, filtered control) at seeded random states:
+    per batch size, the wall latency of a call (enqueue + synchronise) and
+    the device time per call from HIP events."""
+    P = W.quad_x4d(41, 0.5, "x")
+    spec = hjr.Spec.of(P)
+    V, st = hjr.solve(spec, torch.tensor(P.l, dtype=torch.float32, device="cuda"))
+    rng = np.random.default_rng(5)
+    lo, hi = np.array(P.lo), np.array(P.hi)
+    rows = []
+    for n in (1, 64, 4096, 262144, 4194304):
+        X = torch.tensor(lo + (hi - lo) * rng.random((n, 4)), device="cuda")
+        up = torch.tensor(rng.uniform(-0.3, 0.3, (n, 1)), device="cuda")
+        out = hjr.query(spec, V, X, u_perf=up)
+        reps = 200 if n <= 4096 else 20
+        for _ in range(3):
+            hjr.query(spec, V, X, u_perf=up, out=out)
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            hjr.query(spec, V, X, u_perf=up, out=out)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e3)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            hjr.query(spec, V, X, u_perf=up, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        dev_ms = e0.elapsed_time(e1) / reps
+        rows.append(dict(n=n, p50_ms=pct(lat, 50), p99_ms=pct(lat, 99), device_ms=dev_ms,
+                         queries_per_s=n / (dev_ms * 1e-3)))
+        progress(f"query n={n}: p50 {rows[-1]['p50_ms']:.3f} ms, device {dev_ms:.4f} ms")
+    big = rows[-1]
+    # per query: the state (32 B), value, gradient, u*, u_perf and u_out
+    # (8 + 32 + 8 + 8 + 8 B), and the 144 distinct FP32 values of the
+    # corners' stencils (16 corners and, per axis, two more nodes on each
+    # side of the cell: 16 + 4 x 32), which mostly hit in cache
+    bpq = 32 + 64 + 144 * 4
+    achieved = big["queries_per_s"] * bpq / 1e9
+    return {
+        "metric": "safety queries/s",
+        "value": big["queries_per_s"],
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f64 (V stored as f32)",
+        "data": "synthetic",
+        "config": {"workload": "safety query (value, gradient, u*, least-restrictive filter) on "
+                               "the converged 41^4 x-subsystem, uniform random states",
+                   "solve_iterations": st["iterations"]},
+        "batches": rows,
+        "roofline": {"bound": "hbm", "kernel": "k_query<float>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_query": bpq,
+                     "avg_launch_us": big["device_ms"] * 1e3, "queries_per_launch": big["n"]},
+    }
+
+
+# ---------------------------------------------------------------------------
 # batch mode: 256 seeded subsystem solves, plain vs batched
 # ---------------------------------------------------------------------------
 
@@ -624,7 +692,7 @@ def main():
     hjr.lib()
     fn = {"step": mode_step, "batch": mode_batch, "serve": mode_serve, "warm": mode_warm,
           "copy": mode_copy, "precision": mode_precision, "kernels": mode_kernels,
-          "field": mode_field, "field_kernels": mode_field_kernels}[args.mode]
+          "field": mode_field, "field_kernels": mode_field_kernels, "query": mode_query}[args.mode]
     out = fn(args, torch, hjr, W)
     print(json.dumps(out), flush=True)
 

@@ -285,6 +285,51 @@ hjr_status hjr_solve_batch(int32_t n, const hjr_problem* probs, const hjr_opts* 
                            hjr_stats* results);
 
 /* ------------------------------------------------------------------------ */
+/* Safety queries on a converged value function (paper Sec. II-A: the        */
+/* gradient of the converged value gives the optimal safety controller;     */
+/* Sec. II-B: it overrides the learned policy near the safe set's boundary) */
+/* ------------------------------------------------------------------------ */
+
+/* Controls per model: QUAD_Z2D {u}, QUAD_X4D {S}, DI2X2 {u_a, u_b}. */
+typedef struct hjr_query {
+    int64_t n;              /* states queried (0: nothing to do) */
+    const double* x;        /* DEVICE, n x ndim, state-major (x[i ndim + a]) */
+    double* value;          /* DEVICE, n, or NULL: V at x, multilinear
+                               interpolation of the grid values (corner
+                               weights products of t and 1 - t in double, t
+                               the fraction of x in its cell, corners in
+                               row-major order of their offsets) */
+    double* grad;           /* DEVICE, n x ndim, or NULL: the same
+                               interpolation of the node gradients
+                               (p+ + p-)/2 the solver evaluates H with
+                               (hjr_opts.order: 2 = ENO2, 1 = first order) */
+    double* u_star;         /* DEVICE, n x nctrl, or NULL: the optimal safety
+                               control, the control-box vertex maximising
+                               min over d of grad . f(x, u, d): each input at
+                               the bound picked by the sign of its
+                               coefficient in grad . f, the upper bound when
+                               that coefficient is 0 */
+    const double* u_perf;   /* DEVICE, n x nctrl, or NULL: a performance
+                               control to filter */
+    double* u_out;          /* DEVICE, n x nctrl, or NULL (needs u_perf): the
+                               least-restrictive filter, u_perf where
+                               value >= level, else u_star */
+    double level;           /* filter threshold on the value (0 = the safe
+                               set's boundary; a positive level overrides
+                               earlier) */
+} hjr_query;
+
+/* Safety query at n states on the value V (N elements of o->dtype, e.g. the
+ * output of a solve) over grid with model dyn.  Computed in double after
+ * the loads of V.  A state outside the grid box, or with a NaN coordinate,
+ * gets NaN in every output (and u_out = u_star = NaN).  EINVAL for an
+ * invalid model, grid, order or dtype, n < 0, missing x or V with n > 0,
+ * u_out without u_perf, or a NaN level; nothing is enqueued then.
+ * Asynchronous on o->stream. */
+hjr_status hjr_safety_query(const hjr_dyn* dyn, const hjr_grid* grid, const void* V,
+                            const hjr_query* q, const hjr_opts* o);
+
+/* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of safe-set update requests (a request is a  */
 /* new disturbance bound for a subsystem instance, paper Sec. II-C/III-B).   */
 /* ------------------------------------------------------------------------ */

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhjr.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["hjr_kernels.hip", "hjr_engine.cpp", "hjr_api.cpp", "hjr_server.cpp"]
+SOURCES = ["hjr_kernels.hip", "hjr_query.hip", "hjr_engine.cpp", "hjr_api.cpp", "hjr_server.cpp"]
 
 # Packed FP32 instructions are disabled: the kernels are written as scalar
 # float code and must not be turned into v_pk_* forms by the compiler.

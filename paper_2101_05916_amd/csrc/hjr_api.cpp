@@ -522,6 +522,47 @@ hjr_status hjr_solve_batch(int32_t n, const hjr_problem* probs, const hjr_opts* 
     }
 }
 
+hjr_status hjr_safety_query(const hjr_dyn* dyn, const hjr_grid* grid, const void* V,
+                            const hjr_query* q, const hjr_opts* o)
+{
+    const hjr_opts op = resolve(o);
+    if (!dyn || !grid || !q) return HJR_EINVAL;
+    if (op.dtype != HJR_F32 && op.dtype != HJR_F64) return HJR_EINVAL;
+    if (op.order != 1 && op.order != 2) return HJR_EINVAL;
+    if (!grid_valid(*grid) || !dyn_valid(*dyn, *grid)) return HJR_EINVAL;
+    if (q->n < 0 || std::isnan(q->level)) return HJR_EINVAL;
+    if (q->u_out && !q->u_perf) return HJR_EINVAL;
+    if (q->n == 0) return HJR_OK;
+    if (!q->x || !V) return HJR_EINVAL;
+    QueryArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.kind = dyn->kind;
+    A.ndim = grid->ndim;
+    A.order = op.order;
+    A.nctrl = dyn->kind == HJR_DI2X2 ? 2 : 1;
+    int64_t st = 1;
+    for (int a = grid->ndim - 1; a >= 0; a--) {
+        A.n[a] = grid->n[a];
+        A.stride[a] = st;
+        st *= grid->n[a];
+        A.lo[a] = grid->lo[a];
+        A.hi[a] = grid->hi[a];
+        A.h[a] = (grid->hi[a] - grid->lo[a]) / (double)(grid->n[a] - 1);
+        A.hih[a] = 0.5 / A.h[a];
+    }
+    for (int i = 0; i < 16; i++) A.par[i] = dyn->p[i];
+    A.nq = q->n;
+    A.x = q->x;
+    A.value = q->value;
+    A.grad = q->grad;
+    A.u_star = q->u_star;
+    A.u_perf = q->u_perf;
+    A.u_out = q->u_out;
+    A.level = q->level;
+    if (launch_query((hipStream_t)op.stream, op.dtype, A, V) != hipSuccess) return HJR_EDEVICE;
+    return HJR_OK;
+}
+
 hjr_status hjr_interp(const hjr_grid* src, const void* V_src, const hjr_grid* dst, void* V_dst,
                       const void* l_dst, const hjr_opts* o)
 {

@@ -26,6 +26,10 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #ifndef HJR_BLOCKS_PER_CU
 #define HJR_BLOCKS_PER_CU 24         // cap on stage workgroups per CU (6 single-wave groups per SIMD)
 #endif
+#ifndef HJR_BLOCKS_PER_CU_F64
+#define HJR_BLOCKS_PER_CU_F64 14     // the same for the FP64 kernels (15, which their LDS
+                                     // allows, measured 17-20 % slower)
+#endif
 #ifndef HJR_WAVES_PER_EU
 #define HJR_WAVES_PER_EU 0           // occupancy hint for the stage kernels, 0 = none
 #endif

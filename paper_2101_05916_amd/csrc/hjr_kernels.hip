@@ -648,7 +648,8 @@ int stage_blocks_per_cu(int dtype, int stage, int fam)
     int n = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kStageBlock, 0);
     if (e != hipSuccess || n < 1) n = 2;
-    if (HJR_BLOCKS_PER_CU > 0 && HJR_BLOCKS_PER_CU < n) n = HJR_BLOCKS_PER_CU;
+    const int cap = dtype == HJR_F64 ? HJR_BLOCKS_PER_CU_F64 : HJR_BLOCKS_PER_CU;
+    if (cap > 0 && cap < n) n = cap;
     return n;
 }
 

@@ -38,6 +38,32 @@ hipError_t launch_field_check(hipStream_t s, int dtype, const void* f, int nch, 
 // Fill n 64-bit words with value.
 hipError_t launch_fill_u64(hipStream_t s, uint64_t* p, int64_t n, uint64_t value);
 
+// Safety queries (hjr_query.hip): per state, the interpolated value and
+// gradient of a converged V, the optimal safety control and the filtered
+// control.
+struct QueryArgs {
+    int32_t kind;
+    int32_t ndim;
+    int32_t order;
+    int32_t nctrl;           // control inputs of the model
+    int32_t n[4];
+    int64_t stride[4];
+    double lo[4];
+    double hi[4];
+    double h[4];
+    double hih[4];           // 0.5 / h
+    double par[16];
+    int64_t nq;              // states
+    const double* x;         // nq x ndim
+    double* value;           // nq, or null
+    double* grad;            // nq x ndim, or null
+    double* u_star;          // nq x nctrl, or null
+    const double* u_perf;    // nq x nctrl, or null
+    double* u_out;           // nq x nctrl, or null (needs u_perf)
+    double level;
+};
+hipError_t launch_query(hipStream_t s, int dtype, const QueryArgs& A, const void* V);
+
 // Workgroups of a stage kernel that fit on one compute unit.
 int stage_blocks_per_cu(int dtype, int stage, int fam);
 

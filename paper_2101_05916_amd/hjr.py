@@ -26,7 +26,7 @@ EXPORTS = (
     "hjr_interp", "hjr_refine_mask", "hjr_solve_levels", "hjr_batch_workspace_bytes",
     "hjr_solve_batch", "hjr_server_create", "hjr_server_submit", "hjr_server_poll",
     "hjr_server_wait", "hjr_server_read_value", "hjr_server_memory", "hjr_server_destroy",
-    "hjr_solve_field",
+    "hjr_solve_field", "hjr_safety_query",
 )
 
 
@@ -77,6 +77,12 @@ class Problem(C.Structure):
                 ("grids", Grid * 4), ("l", C.c_void_p * 4), ("V", C.c_void_p * 4),
                 ("V0", C.c_void_p), ("d", Dstb * 2), ("tol", C.c_double),
                 ("tile_rows", C.c_int32 * 4), ("band", C.c_double), ("dfield", C.c_void_p * 4)]
+
+
+class Query(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("value", C.c_void_p),
+                ("grad", C.c_void_p), ("u_star", C.c_void_p), ("u_perf", C.c_void_p),
+                ("u_out", C.c_void_p), ("level", C.c_double)]
 
 
 class ServerCfg(C.Structure):
@@ -135,6 +141,8 @@ def lib() -> C.CDLL:
     L.hjr_solve_field.restype = st
     L.hjr_solve_field.argtypes = [P(Dyn), C.c_int32, P(Grid), P(C.c_void_p), P(C.c_void_p),
                                   C.c_void_p, C.c_double, P(Opts), P(C.c_void_p), P(Stats)]
+    L.hjr_safety_query.restype = st
+    L.hjr_safety_query.argtypes = [P(Dyn), P(Grid), C.c_void_p, P(Query), P(Opts)]
     L.hjr_batch_workspace_bytes.restype = st
     L.hjr_batch_workspace_bytes.argtypes = [C.c_int32, P(Problem), P(Opts), P(C.c_size_t)]
     L.hjr_solve_batch.restype = st
@@ -478,6 +486,65 @@ def refine_mask(n, lo, hi, V):
     _raise(lib().hjr_refine_mask(C.byref(g), _ptr(V), _ptr(m), C.byref(cnt), C.byref(o)),
            "hjr_refine_mask")
     return m, cnt.value
+
+
+# ---------------------------------------------------------------------------
+# safety queries
+# ---------------------------------------------------------------------------
+
+def controls(kind: int) -> int:
+    """Control inputs of a model (1, or 2 for DI2X2)."""
+    return 2 if kind == DI2X2 else 1
+
+
+def query(spec: Spec, V, X, *, order=2, u_perf=None, level=0.0, grad=True, u_star=True,
+          stream=None, out=None):
+    """Safety query (hjr_safety_query) at the states X (device float64
+    tensor, n x ndim) on the converged value V (device tensor of spec.size
+    elements, float32 or float64).  Returns a dict of device float64 tensors:
+    value (n,), grad (n, ndim), u_star (n, controls) and, when u_perf
+    (n, controls) is given, u_out = u_perf where value >= level else u_star.
+    out: optional dict of preallocated output tensors of those names.
+    Asynchronous on the stream (default: the current one)."""
+    torch = _torch()
+    _check_tensor(V, spec.size, V.dtype, "V")
+    D = len(spec.n)
+    m = controls(spec.kind)
+    if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float64
+            and X.is_contiguous() and X.dim() == 2 and X.shape[1] == D):
+        raise ValueError(f"X must be a contiguous CUDA float64 tensor of shape (n, {D})")
+    n = X.shape[0]
+    res = dict(out or {})
+    dev = X.device
+
+    def buf(name, shape, want):
+        if not want:
+            return None
+        if name not in res:
+            res[name] = torch.empty(shape, dtype=torch.float64, device=dev)
+        return res[name]
+
+    q = Query()
+    q.n = n
+    q.x = X.data_ptr()
+    q.value = buf("value", (n,), True).data_ptr()
+    g = buf("grad", (n, D), grad)
+    q.grad = g.data_ptr() if g is not None else None
+    u = buf("u_star", (n, m), u_star)
+    q.u_star = u.data_ptr() if u is not None else None
+    if u_perf is not None:
+        if not (u_perf.is_cuda and u_perf.dtype == torch.float64 and u_perf.is_contiguous()
+                and u_perf.numel() == n * m):
+            raise ValueError(f"u_perf must be a contiguous CUDA float64 tensor of {n} x {m}")
+        q.u_perf = u_perf.data_ptr()
+        q.u_out = buf("u_out", (n, m), True).data_ptr()
+    q.level = float(level)
+    o = make_opts(V.dtype, order, stream=stream)
+    g_ = make_grid(spec.n, spec.lo, spec.hi)
+    dyn = make_dyn(spec.kind, spec.params)
+    _raise(lib().hjr_safety_query(C.byref(dyn), C.byref(g_), _ptr(V), C.byref(q), C.byref(o)),
+           "hjr_safety_query")
+    return res
 
 
 # ---------------------------------------------------------------------------

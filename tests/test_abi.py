@@ -39,9 +39,9 @@ def test_struct_layouts_match_c():
 #include <stddef.h>
 #include "hjr.h"
 int main(void){
- printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hjr_grid), sizeof(hjr_dyn),
+ printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hjr_grid), sizeof(hjr_dyn),
    sizeof(hjr_dstb), sizeof(hjr_opts), sizeof(hjr_stats), sizeof(hjr_problem),
-   sizeof(hjr_server_cfg), sizeof(hjr_request), sizeof(hjr_reply));
+   sizeof(hjr_server_cfg), sizeof(hjr_request), sizeof(hjr_reply), sizeof(hjr_query));
  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(hjr_opts, flags),
    offsetof(hjr_stats, kernel_launches), offsetof(hjr_problem, tol), offsetof(hjr_request, cold),
    offsetof(hjr_problem, dfield), offsetof(hjr_request, dfield));
@@ -56,7 +56,7 @@ int main(void){
     got = [int(x) for x in out]
     want = [C.sizeof(hjr.Grid), C.sizeof(hjr.Dyn), C.sizeof(hjr.Dstb), C.sizeof(hjr.Opts),
             C.sizeof(hjr.Stats), C.sizeof(hjr.Problem), C.sizeof(hjr.ServerCfg),
-            C.sizeof(hjr.Request), C.sizeof(hjr.Reply),
+            C.sizeof(hjr.Request), C.sizeof(hjr.Reply), C.sizeof(hjr.Query),
             hjr.Opts.flags.offset, hjr.Stats.kernel_launches.offset, hjr.Problem.tol.offset,
             hjr.Request.cold.offset, hjr.Problem.dfield.offset, hjr.Request.dfield.offset]
     assert got == want
@@ -177,6 +177,35 @@ def test_field_solve_rejects_invalid_without_device():
     assert L.hjr_solve_field(C.byref(dyn), 1, g, p, p, None, 0.0, C.byref(o), q, None) == hjr.EINVAL
     bad = (hjr.Grid * 1)(hjr.make_grid((2, 11), (0, -4), (3, 4)))
     assert L.hjr_solve_field(C.byref(dyn), 1, bad, p, p, None, 1e-4, C.byref(o), q, None) == hjr.EINVAL
+
+
+def test_safety_query_rejects_invalid_without_device():
+    L = hjr.lib()
+    dyn = hjr.make_dyn(hjr.QUAD_Z2D, (0.91, 9.81, 7.0, 16.0))
+    g = hjr.make_grid((11, 11), (0, -4), (3, 4))
+    V = C.c_void_p(0x1000)
+    o = hjr.Opts()
+    L.hjr_opts_default(C.byref(o))
+    q = hjr.Query()
+    q.n = 0
+    assert L.hjr_safety_query(C.byref(dyn), C.byref(g), V, C.byref(q), C.byref(o)) == hjr.OK
+    q.n = -1
+    assert L.hjr_safety_query(C.byref(dyn), C.byref(g), V, C.byref(q), C.byref(o)) == hjr.EINVAL
+    q.n = 4  # states but no x
+    assert L.hjr_safety_query(C.byref(dyn), C.byref(g), V, C.byref(q), C.byref(o)) == hjr.EINVAL
+    q.x = 0x2000
+    q.u_out = 0x3000  # filter output without a performance control
+    assert L.hjr_safety_query(C.byref(dyn), C.byref(g), V, C.byref(q), C.byref(o)) == hjr.EINVAL
+    q.u_out = None
+    q.level = float("nan")
+    assert L.hjr_safety_query(C.byref(dyn), C.byref(g), V, C.byref(q), C.byref(o)) == hjr.EINVAL
+    q.level = 0.0
+    o.order = 3
+    assert L.hjr_safety_query(C.byref(dyn), C.byref(g), V, C.byref(q), C.byref(o)) == hjr.EINVAL
+    o.order = 2
+    bad = hjr.make_dyn(hjr.QUAD_X4D, (9.81, 8.0, 10.0, 10.0, 0.35))  # 4-D model on a 2-D grid
+    assert L.hjr_safety_query(C.byref(bad), C.byref(g), V, C.byref(q), C.byref(o)) == hjr.EINVAL
+    assert L.hjr_safety_query(C.byref(dyn), C.byref(g), None, C.byref(q), C.byref(o)) == hjr.EINVAL
 
 
 def test_batch_and_server_reject_invalid():
