@@ -35,6 +35,7 @@ int orc_state_dim(int kind)
     switch (kind) {
     case ORC_QUAD_Z2D: return 2;
     case ORC_QUAD_X4D: return 4;
+    case ORC_QUAD_X4DV: return 4;
     case ORC_DI2X2: return 4;
     default: return 0;
     }
@@ -45,6 +46,7 @@ int orc_num_ctrl(int kind)
     switch (kind) {
     case ORC_QUAD_Z2D: return 1;
     case ORC_QUAD_X4D: return 1;
+    case ORC_QUAD_X4DV: return 1;
     case ORC_DI2X2: return 2;
     default: return 0;
     }
@@ -55,6 +57,7 @@ int orc_num_dstb(int kind)
     switch (kind) {
     case ORC_QUAD_Z2D: return 1;
     case ORC_QUAD_X4D: return 1;
+    case ORC_QUAD_X4DV: return 1;
     case ORC_DI2X2: return 2;
     default: return 0;
     }
@@ -92,6 +95,14 @@ void orc_dynamics(const orc_dyn* dyn, const double* x, const double* u,
         f[2] = -p[1] * x[2] + x[3];
         f[3] = -p[2] * x[2] + p[3] * u[0];
         break;
+    case ORC_QUAD_X4DV:
+        /* the x rows of the 10-D model: x' = vx ; vx' = g tan(theta) + d ;
+         * theta' = -d1 theta + omega ; omega' = -d0 theta + n0 S */
+        f[0] = x[1];
+        f[1] = p[0] * memo_tan(x[2]) + d[0];
+        f[2] = -p[1] * x[2] + x[3];
+        f[3] = -p[2] * x[2] + p[3] * u[0];
+        break;
     case ORC_DI2X2: {
         int za = (int)p[8], va = (int)p[9], zb = (int)p[10], vb = (int)p[11];
         f[za] = x[va];
@@ -114,6 +125,7 @@ void orc_ctrl_box(const orc_dyn* dyn, double* lo, double* hi)
         hi[0] = p[3];
         break;
     case ORC_QUAD_X4D:
+    case ORC_QUAD_X4DV:
         lo[0] = -p[4];
         hi[0] = p[4];
         break;
@@ -739,4 +751,39 @@ int orc_query(const orc_dyn* dyn, const orc_grid* g, const double* V, int order,
         }
     }
     return ORC_OK;
+}
+
+int orc_query_decomposed(int nsub, const orc_dyn* dyns, const orc_grid* grids,
+                         const double* const* Vs, const int32_t* state_index,
+                         const int32_t* control_index, const double* const* dlo,
+                         const double* const* dhi, int order, const double* x,
+                         double level, const double* u_perf, double* value,
+                         int32_t* active, double* sub_value, double* grad,
+                         double* u_star, double* u_out)
+{
+    int status = ORC_OK;
+    double best = INFINITY;
+    int arg = -1;
+    for (int s = 0; s < nsub; s++) {
+        int D = grids[s].ndim, m = orc_num_ctrl(dyns[s].kind);
+        double xs[4], v, g[4], u[4];
+        for (int a = 0; a < D; a++) xs[a] = x[state_index[4 * s + a]];
+        if (orc_query(&dyns[s], &grids[s], Vs[s], order, dlo[s], dhi[s], xs, &v, g, u) != ORC_OK)
+            status = ORC_EINVAL;
+        sub_value[s] = v;
+        for (int a = 0; a < D; a++) grad[state_index[4 * s + a]] = g[a];
+        for (int k = 0; k < m; k++) {
+            int c = control_index[s] + k;
+            u_star[c] = u[k];
+            /* each subsystem's own inputs are filtered on its own value */
+            u_out[c] = (v >= level) ? u_perf[c] : u[k];
+        }
+        if (v < best) { /* the first subsystem attaining the minimum */
+            best = v;
+            arg = s;
+        }
+    }
+    *value = status == ORC_OK ? best : NAN;
+    *active = status == ORC_OK ? arg : -1;
+    return status;
 }

@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-enum { ORC_QUAD_Z2D = 0, ORC_QUAD_X4D = 1, ORC_DI2X2 = 2 };
+enum { ORC_QUAD_Z2D = 0, ORC_QUAD_X4D = 1, ORC_DI2X2 = 2, ORC_QUAD_X4DV = 3 };
 
 enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_NOT_CONVERGED = 3 };
 
@@ -46,6 +46,11 @@ typedef struct orc_grid {
  *                 f = (vz, k*u - g + d),  u in [u_lo, u_hi], d channel 0.
  *   ORC_QUAD_X4D  state (x, vx, theta, omega):  p = {g, d1, d0, n0, s_max}
  *                 f = (vx + d, g*tan(theta), -d1*theta + omega, -d0*theta + n0*S)
+ *                 S in [-s_max, s_max], d channel 0.
+ *   ORC_QUAD_X4DV the x-subsystem as the 10-D model of Sec. IV writes it,
+ *                 with the disturbance on the velocity rate:
+ *                 p = {g, d1, d0, n0, s_max}
+ *                 f = (vx, g*tan(theta) + d, -d1*theta + omega, -d0*theta + n0*S)
  *                 S in [-s_max, s_max], d channel 0.
  *   ORC_DI2X2     two QUAD_Z2D copies "a" and "b" on a 4-D grid:
  *                 p = {k_a, g_a, ulo_a, uhi_a, k_b, g_b, ulo_b, uhi_b,
@@ -200,6 +205,26 @@ int orc_solve_field(const orc_dyn* dyn, const orc_grid* g, const double* l,
 int orc_query(const orc_dyn* dyn, const orc_grid* g, const double* V, int order,
               const double* dlo, const double* dhi, const double* x,
               double* value, double* grad, double* u_star);
+
+/* Decomposed query (Sec. III-A: a system decoupled into subsystems has the
+ * product of their safe sets, so its value is the minimum of theirs, and
+ * each subsystem's safety controller drives its own inputs).  Subsystem s
+ * has model dyns[s], grid grids[s], value Vs[s] and disturbance box dlo[s],
+ * dhi[s]; its axis a is component state_index[4 s + a] of the full state x,
+ * its controls start at control_index[s] of the full control vector.
+ * Outputs: sub_value[s] (orc_query of each subsystem at its part of x),
+ * value = the minimum, active = the first subsystem attaining it, grad and
+ * u_star scattered to the full state / control vectors, and u_out: per
+ * subsystem, its inputs from u_perf where its own value >= level, else its
+ * u_star.  Returns ORC_EINVAL (value NaN, active -1) if any part of x lies
+ * outside its subsystem's grid box. */
+int orc_query_decomposed(int nsub, const orc_dyn* dyns, const orc_grid* grids,
+                         const double* const* Vs, const int32_t* state_index,
+                         const int32_t* control_index, const double* const* dlo,
+                         const double* const* dhi, int order, const double* x,
+                         double level, const double* u_perf, double* value,
+                         int32_t* active, double* sub_value, double* grad,
+                         double* u_star, double* u_out);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liborc.so")
 _SRC = os.path.join(_HERE, "hjr_oracle.c")
 
-QUAD_Z2D, QUAD_X4D, DI2X2 = 0, 1, 2
+QUAD_Z2D, QUAD_X4D, DI2X2, QUAD_X4DV = 0, 1, 2, 3
 OK, EINVAL, NOT_CONVERGED = 0, 1, 3
 
 
@@ -94,6 +94,11 @@ def lib():
         L.orc_iterate_at_field.restype = C.c_double
         L.orc_iterate_at_field.argtypes = [yp, gp, dp, dp, dp, dp, C.c_double, C.c_int, dp,
                                            dp, C.c_int64]
+        L.orc_query_decomposed.restype = C.c_int
+        L.orc_query_decomposed.argtypes = [C.c_int, yp, gp, C.POINTER(dp), C.POINTER(C.c_int32),
+                                           C.POINTER(C.c_int32), C.POINTER(dp), C.POINTER(dp),
+                                           C.c_int, dp, C.c_double, dp, dp,
+                                           C.POINTER(C.c_int32), dp, dp, dp, dp]
         L.orc_query.restype = C.c_int
         L.orc_query.argtypes = [yp, gp, dp, C.c_int, dp, dp, dp, dp, dp, dp]
         L.orc_solve_field.restype = C.c_int
@@ -307,3 +312,43 @@ def query(dyn: Dyn, grid: Grid, V, X, dlo, dhi, order=2):
         u[i] = ub[:m]
         ok[i] = st == OK
     return dict(value=val, grad=grad, u=u, ok=ok)
+
+
+def query_decomposed(subs, X, level=0.0, U_perf=None, order=2):
+    """Decomposed query at every row of X (full states).  subs: list of
+    dicts with dyn, grid, V, state_index (list), control_index, dlo, dhi.
+    Returns dict(value, active, sub_value (n, nsub), grad (n, state_dim),
+    u (n, controls), u_out, ok)."""
+    X = np.atleast_2d(_f64(X))
+    n, dim = X.shape
+    ns = len(subs)
+    dyns = (Dyn * ns)(*[s["dyn"] for s in subs])
+    grids = (Grid * ns)(*[s["grid"] for s in subs])
+    Vs = [_f64(s["V"]) for s in subs]
+    Vp = (C.POINTER(C.c_double) * ns)(*[_dp(v) for v in Vs])
+    sidx = np.zeros(4 * ns, dtype=np.int32)
+    for k, sb in enumerate(subs):
+        sidx[4 * k: 4 * k + len(sb["state_index"])] = sb["state_index"]
+    cidx = np.array([sb["control_index"] for sb in subs], dtype=np.int32)
+    m = int(max(sb["control_index"] + (2 if sb["dyn"].kind == DI2X2 else 1) for sb in subs))
+    bounds = [_dbounds(sb["dlo"], sb["dhi"]) for sb in subs]
+    lo_p = (C.POINTER(C.c_double) * ns)(*[_dp(b[0]) for b in bounds])
+    hi_p = (C.POINTER(C.c_double) * ns)(*[_dp(b[1]) for b in bounds])
+    U = np.zeros((n, m)) if U_perf is None else np.atleast_2d(_f64(U_perf))
+    out = dict(value=np.zeros(n), active=np.zeros(n, dtype=np.int32), sub_value=np.zeros((n, ns)),
+               grad=np.zeros((n, dim)), u=np.zeros((n, m)), u_out=np.zeros((n, m)),
+               ok=np.zeros(n, dtype=bool))
+    v, a = C.c_double(0), C.c_int32(0)
+    sv, g, u, uo = np.zeros(ns), np.zeros(dim), np.zeros(m), np.zeros(m)
+    ip = C.POINTER(C.c_int32)
+    for i in range(n):
+        xi = _f64(X[i])
+        ui = _f64(U[i])
+        st = lib().orc_query_decomposed(ns, dyns, grids, Vp, sidx.ctypes.data_as(ip),
+                                        cidx.ctypes.data_as(ip), lo_p, hi_p, int(order), _dp(xi),
+                                        float(level), _dp(ui), C.byref(v), C.byref(a), _dp(sv),
+                                        _dp(g), _dp(u), _dp(uo))
+        out["value"][i], out["active"][i] = v.value, a.value
+        out["sub_value"][i], out["grad"][i], out["u"][i], out["u_out"][i] = sv, g, u, uo
+        out["ok"][i] = st == OK
+    return out

@@ -18,6 +18,14 @@ l > 0 inside the constraint set:
   l = 4 - |x|.
 * DI2X2 (test-only): two independent vertical models on one 4-D grid, in any
   assignment of their four coordinates to the grid axes.
+* the 10-D model as Sec. IV writes it (`decomposed_quad10d_paper`): x- and
+  y-subsystems with the disturbance on the velocity rate,
+  x' = vx, vx' = 9.81 tan(theta) + d, theta' = -8 theta + omega,
+  omega' = -10 theta + 10 S, |S| <= 14 deg; z-subsystem
+  z' = vz, vz' = T - 9.81 + d with the thrust acceleration T in
+  [0.6 g, 1.4 g] (the printed k_T and thrust bounds taken as thrust-to-weight
+  limits, so that hovering is feasible); constraint sets of the 10-D demo
+  (Sec. V): |p| <= 2.5, |v| <= 3.5, |theta| <= pi/8, 0.35 <= z <= 2.8.
 
 The paper's own workloads come from a simulator and GP-learned bounds that
 are not available; scalar symmetric disturbance bounds [-dbar, dbar] stand in,
@@ -32,7 +40,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-QUAD_Z2D, QUAD_X4D, DI2X2 = 0, 1, 2
+QUAD_Z2D, QUAD_X4D, DI2X2, QUAD_X4DV = 0, 1, 2, 3
 
 Z2D_PARAMS = (0.91, 9.81, 7.0, 16.0)           # k, g, u_lo, u_hi
 X4D_PARAMS = (9.81, 8.0, 10.0, 10.0, math.pi / 9)  # g, d1, d0, n0, s_max
@@ -130,6 +138,52 @@ def di2x2(n=21, perm=(0, 1, 2, 3), dbar=(0.5, 0.3), name="di2x2") -> Problem:
     params = Z2D_PARAMS + Z2D_PARAMS + tuple(float(p) for p in perm)
     return Problem(DI2X2, params, nn, tuple(lo), tuple(hi), l,
                    (-dbar[0], -dbar[1]), (dbar[0], dbar[1]), name=name)
+
+
+# The 10-D model of Sec. IV with its own parameters and the constraint sets
+# of the 10-D demo of Sec. V.
+X4DV_PARAMS = (9.81, 8.0, 10.0, 10.0, 14.0 * math.pi / 180.0)  # g, d1, d0, n0, s_max
+X4DV_BOX = ((-3.0, -4.0, -math.pi / 6, -4.0), (3.0, 4.0, math.pi / 6, 4.0))
+Z10_PARAMS = (1.0, 9.81, 0.6 * 9.81, 1.4 * 9.81)  # k = 1, g, thrust acceleration bounds
+Z10_BOX = ((0.0, -4.5), (3.2, 4.5))
+
+
+def l_x4dv(n, lo=X4DV_BOX[0], hi=X4DV_BOX[1], pmax=2.5, vmax=3.5, thmax=math.pi / 8):
+    """|px| <= pmax, |vx| <= vmax, |theta| <= thmax: the smallest margin
+    (positive inside)."""
+    G = mesh(n, lo, hi)
+    return np.minimum(np.minimum(pmax - np.abs(G[0]), vmax - np.abs(G[1])),
+                      thmax - np.abs(G[2])).ravel()
+
+
+def l_z10(n, lo=Z10_BOX[0], hi=Z10_BOX[1], zmin=0.35, zmax=2.8, vmax=3.5):
+    Z, VZ = mesh(n, lo, hi)
+    return np.minimum(np.minimum(Z - zmin, zmax - Z), vmax - np.abs(VZ)).ravel()
+
+
+def quad_x4dv(n=41, dbar=0.3, name="x4dv", tol=TOL, band=0.0) -> Problem:
+    nn = (n,) * 4 if np.isscalar(n) else tuple(n)
+    return Problem(QUAD_X4DV, X4DV_PARAMS, nn, X4DV_BOX[0], X4DV_BOX[1], l_x4dv(nn),
+                   (-dbar,), (dbar,), tol=tol, name=name, band=band)
+
+
+def quad_z10(n=101, dbar=0.3, name="z10") -> Problem:
+    nn = (n, n) if np.isscalar(n) else tuple(n)
+    return Problem(QUAD_Z2D, Z10_PARAMS, nn, Z10_BOX[0], Z10_BOX[1], l_z10(nn),
+                   (-dbar,), (dbar,), name=name)
+
+
+def decomposed_quad10d_paper(n4=41, n2=101, dbar=0.3):
+    """The 10-D model as the paper writes it, split into x, y (4-D, the
+    disturbance on the velocity rate) and z (2-D); initial bound +-0.3, the
+    paper's 3-sigma bound for sigma^2 = 0.01."""
+    return [quad_x4dv(n4, dbar, "x"), quad_x4dv(n4, dbar, "y"), quad_z10(n2, dbar, "z")]
+
+
+# Full 10-D state (px, vx, thx, wx, py, vy, thy, wy, pz, vz) and controls
+# (Sx, Sy, Tz): the subsystems' axes and control slots in them.
+QUAD10D_STATE_INDEX = ((0, 1, 2, 3), (4, 5, 6, 7), (8, 9))
+QUAD10D_CONTROL_INDEX = (0, 1, 2)
 
 
 def decomposed_quad10d(n4=41, n2=101, dbar=0.5):
@@ -245,3 +299,15 @@ def with_field(P: Problem, dfield: np.ndarray, name: str | None = None) -> Probl
                 tuple(float(f[c, 1].max()) for c in range(f.shape[0])),
                 tol=P.tol, name=name or P.name, band=P.band, meta=dict(P.meta), dfield=f)
     return Q
+
+
+def wind_x4dv(n=41, peak=2.0, x0=2.5, width=1.0, sigma=0.1, sigma_speed=0.05) -> np.ndarray:
+    """Bound on the 10-D model's x-disturbance (an acceleration) after a wind
+    update: mean a Gaussian bump of `peak` m/s^2 at px = x0 (wind near the
+    wall, Sec. V), standard deviation sigma + sigma_speed |vx| / 3.5; far
+    from the bump at vx = 0 the interval is the initial +-0.3."""
+    nn = (n,) * 4 if np.isscalar(n) else tuple(n)
+    G = mesh(nn, X4DV_BOX[0], X4DV_BOX[1])
+    mu = peak * np.exp(-0.5 * ((G[0] - x0) / width) ** 2)
+    sig = sigma + sigma_speed * np.abs(G[1]) / 3.5
+    return gp_bound(mu, sig)
