@@ -23,7 +23,10 @@ coarse-to-fine vs cold on the 4-D x-subsystem), --mode field (the same
 decomposed solve with state-dependent disturbance bounds, a per-node
 interval on every grid level, and the roofline of its stage-2 kernel),
 --mode query (safety queries -- value, gradient, optimal control, filter --
-on the converged 41^4 x-subsystem: latency per call and queries/s).
+on the converged 41^4 x-subsystem: latency per call and queries/s), --mode
+quad10d (the 10-D model as the paper writes it: initial safe set, then a
+GP-bound update warm-started from the restricted previous value, coarse to
+fine, and 10-D decomposed queries on the result).
 """
 from __future__ import annotations
 
@@ -47,7 +50,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "warm", "copy", "precision", "kernels",
-                             "field", "field_kernels", "query"])
+                             "field", "field_kernels", "query", "quad10d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk", type=int, default=None, help="RK2 steps per chunk (default: autotuned)")
@@ -424,6 +427,117 @@ def mode_query(args, torch, hjr, W):
 
 
 # ---------------------------------------------------------------------------
+# quad10d mode: the 10-D model of the paper, initial safe set and update
+# ---------------------------------------------------------------------------
+
+def mode_quad10d(args, torch, hjr, W):
+    """x, y (the 10-D model's x-subsystem form, 21^4 -> 41^4, band 0.5) and
+    z (51^2 -> 101^2): (1) the initial safe set for the bound +-0.3, cold,
+    coarse to fine; (2) the update for GP-shaped per-node bounds (wind near
+    a wall for x, y; the vertical wind for z), each level with its own
+    field, started on the coarse grid from the previous fine value
+    restricted to it; (3) decomposed queries of 10-D states on the updated
+    values.  FP32; the 4-D residuals over the band 0.1 (workloads.BAND_X4DV)."""
+    levels = {"x": (W.quad_x4dv, [21, 41]), "y": (W.quad_x4dv, [21, 41]),
+              "z": (W.quad_z10, [51, 101])}
+
+    def fields_for(name, n):
+        if name == "z":
+            nn = (n, n)
+            Z = W.mesh(nn, W.Z10_BOX[0], W.Z10_BOX[1])[0]
+            mu = 1.5 * np.exp(-0.5 * ((Z - 0.6) / 0.3) ** 2)
+            return W.gp_bound(mu, 0.1 + 0.05 * np.abs(Z - 1.5))
+        return W.wind_x4dv(n)
+
+    jobs = []
+    for name, (mk, ns) in levels.items():
+        lv, fs = [], []
+        for n in ns:
+            P = mk(n, 0.3, name)
+            l = torch.tensor(P.l, dtype=torch.float32, device="cuda")
+            lv.append((P.n, l, torch.empty_like(l)))
+            fs.append(torch.tensor(fields_for(name, n), dtype=torch.float32, device="cuda"))
+        P = mk(ns[-1], 0.3, name)
+        if P.ndim == 4:
+            P.band = W.BAND_X4DV
+        jobs.append((name, hjr.Spec.of(P), lv, fs, ns))
+
+    def initial():
+        probs = [hjr.make_problem(spec, None, None, levels=lv) for _, spec, lv, _, _ in jobs]
+        return hjr.solve_batch(probs, dtype=torch.float32, chunk=args.chunk)
+
+    def update(prev):
+        probs = []
+        for (name, spec, lv, fs, ns), Vfine in zip(jobs, prev):
+            V0 = hjr.interp(lv[-1][0], Vfine, lv[0][0], spec.lo, spec.hi)
+            lv2 = [(n, l, torch.empty_like(l)) for n, l, _ in lv]
+            probs.append((hjr.make_problem(spec, None, None, V0=V0, levels=lv2, dfields=fs), lv2, V0))
+        r, st = hjr.solve_batch([p for p, _, _ in probs], dtype=torch.float32, chunk=args.chunk)
+        return r, st, [lv2[-1][2] for _, lv2, _ in probs]
+
+    def timed(fn, reps):
+        out, ts = None, []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return out, ts
+
+    initial()
+    (r0, st0), t_init = timed(initial, args.steps)
+    prev = [lv[-1][2].clone() for _, _, lv, _, _ in jobs]
+    update(prev)
+    (r1, st1, Vnew), t_upd = timed(lambda: update(prev), args.steps)
+    cu0 = sum(s["cell_updates"] for s in st0)
+    cu1 = sum(s["cell_updates"] for s in st1)
+    # 10-D decomposed queries on the updated values
+    subs = [(spec, V, si, c) for (_, spec, _, _, _), V, si, c in
+            zip(jobs, Vnew, W.QUAD10D_STATE_INDEX, W.QUAD10D_CONTROL_INDEX)]
+    lo = np.array(sum((tuple(sp.lo) for _, sp, _, _, _ in jobs), ()))
+    hi = np.array(sum((tuple(sp.hi) for _, sp, _, _, _ in jobs), ()))
+    rng = np.random.default_rng(10)
+    qrows = []
+    for n in (1, 4096, 1048576):
+        X = torch.tensor(lo + (hi - lo) * rng.random((n, 10)), device="cuda")
+        out = hjr.query_decomposed(subs, X)
+        lat = []
+        for _ in range(50 if n <= 4096 else 10):
+            t0 = time.perf_counter()
+            hjr.query_decomposed(subs, X, out=out)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e3)
+        qrows.append(dict(n=n, p50_ms=pct(lat, 50), p99_ms=pct(lat, 99),
+                          queries_per_s=n / (pct(lat, 50) * 1e-3),
+                          safe_fraction=float((out["value"] >= 0).float().mean())))
+        progress(f"10-D query n={n}: p50 {qrows[-1]['p50_ms']:.3f} ms")
+    ms_upd = pct(t_upd, 50)
+    return {
+        "metric": "grid cell-updates/s",
+        "value": cu1 / (ms_upd * 1e-3),
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "10-D near-hover quadcopter as the paper writes it (x, y with the "
+                               "disturbance on the velocity rate, |S| <= 14 deg; z thrust "
+                               "acceleration in [0.6 g, 1.4 g]); safe-set update for GP-shaped "
+                               "per-node bounds, warm-started from the restricted previous "
+                               "value, 21^4 -> 41^4 (band 0.1) and 51^2 -> 101^2"},
+        "initial": {"ms_p50": pct(t_init, 50), "cell_updates": cu0,
+                    "iterations_per_level": {j[0]: s["level_iterations"][:2] for j, s in zip(jobs, st0)},
+                    "status": [s["status"] for s in st0]},
+        "update": {"ms_p50": ms_upd, "ms_p99": pct(t_upd, 99), "cell_updates": cu1,
+                   "iterations_per_level": {j[0]: s["level_iterations"][:2] for j, s in zip(jobs, st1)},
+                   "status": [s["status"] for s in st1]},
+        "query_10d": qrows,
+    }
+
+
+# ---------------------------------------------------------------------------
 # batch mode: 256 seeded subsystem solves, plain vs batched
 # ---------------------------------------------------------------------------
 
@@ -692,7 +806,8 @@ def main():
     hjr.lib()
     fn = {"step": mode_step, "batch": mode_batch, "serve": mode_serve, "warm": mode_warm,
           "copy": mode_copy, "precision": mode_precision, "kernels": mode_kernels,
-          "field": mode_field, "field_kernels": mode_field_kernels, "query": mode_query}[args.mode]
+          "field": mode_field, "field_kernels": mode_field_kernels, "query": mode_query,
+          "quad10d": mode_quad10d}[args.mode]
     out = fn(args, torch, hjr, W)
     print(json.dumps(out), flush=True)
 

@@ -80,12 +80,17 @@ enum hjr_dtype { HJR_F32 = 0, HJR_F64 = 1 };
  *                x' = vx + d, vx' = g tan(theta), theta' = -d1 theta + omega,
  *                omega' = -d0 theta + n0 S,  |S| <= s_max.
  *                p = {g, d1, d0, n0, s_max}; disturbance channel 0.
+ *  HJR_QUAD_X4DV the x-subsystem as the 10-D model of Sec. IV, eq. (3)
+ *                writes it, with the disturbance on the velocity rate:
+ *                x' = vx, vx' = g tan(theta) + d, theta' = -d1 theta + omega,
+ *                omega' = -d0 theta + n0 S,  |S| <= s_max.
+ *                p = {g, d1, d0, n0, s_max}; disturbance channel 0.
  *  HJR_DI2X2     test model: two independent QUAD_Z2D systems a, b on one
  *                4-D grid; p = {k_a, g_a, ulo_a, uhi_a, k_b, g_b, ulo_b,
  *                uhi_b, axis(z_a), axis(v_a), axis(z_b), axis(v_b)} (axes as
  *                doubles, a permutation of 0..3); channel 0 acts on a, 1 on b.
  */
-enum hjr_dyn_kind { HJR_QUAD_Z2D = 0, HJR_QUAD_X4D = 1, HJR_DI2X2 = 2 };
+enum hjr_dyn_kind { HJR_QUAD_Z2D = 0, HJR_QUAD_X4D = 1, HJR_DI2X2 = 2, HJR_QUAD_X4DV = 3 };
 
 typedef struct hjr_grid {
     int32_t ndim;
@@ -290,7 +295,7 @@ hjr_status hjr_solve_batch(int32_t n, const hjr_problem* probs, const hjr_opts* 
 /* Sec. II-B: it overrides the learned policy near the safe set's boundary) */
 /* ------------------------------------------------------------------------ */
 
-/* Controls per model: QUAD_Z2D {u}, QUAD_X4D {S}, DI2X2 {u_a, u_b}. */
+/* Controls per model: QUAD_Z2D {u}, QUAD_X4D and QUAD_X4DV {S}, DI2X2 {u_a, u_b}. */
 typedef struct hjr_query {
     int64_t n;              /* states queried (0: nothing to do) */
     const double* x;        /* DEVICE, n x ndim, state-major (x[i ndim + a]) */
@@ -328,6 +333,54 @@ typedef struct hjr_query {
  * Asynchronous on o->stream. */
 hjr_status hjr_safety_query(const hjr_dyn* dyn, const hjr_grid* grid, const void* V,
                             const hjr_query* q, const hjr_opts* o);
+
+/* Decomposed system (paper Sec. III-A): subsystems that share no state and
+ * no input have the product of their safe sets, so the full value is the
+ * minimum of theirs, and each subsystem's safety controller drives its own
+ * inputs.  A subsystem's axis a is component state_index[a] of the full
+ * state; its controls start at component control_index of the full control
+ * vector (e.g. the near-hover quadcopter: x on (px, vx, thx, wx) = (0, 1, 2,
+ * 3) and control 0, y on (4, 5, 6, 7) and control 1, z on (8, 9) and
+ * control 2). */
+typedef struct hjr_subsystem {
+    hjr_dyn dyn;
+    hjr_grid grid;
+    const void* V;            /* DEVICE, its converged value (hjr_opts.dtype) */
+    int32_t state_index[4];   /* full-state component of each axis; distinct
+                                 across subsystems */
+    int32_t control_index;
+    int32_t reserved;
+} hjr_subsystem;
+
+typedef struct hjr_query_decomposed {
+    int64_t n;                /* states queried */
+    int32_t state_dim;        /* full state dimension (<= 32) */
+    int32_t control_dim;      /* full control dimension */
+    const double* x;          /* DEVICE, n x state_dim */
+    double* sub_value;        /* DEVICE, n x nsub: each subsystem's value
+                                 (required: also the scratch of the min) */
+    double* value;            /* DEVICE, n, or NULL: min over subsystems (NaN
+                                 if a part of the state is outside its box) */
+    int32_t* active;          /* DEVICE, n, or NULL: the first subsystem
+                                 attaining the min, -1 with a NaN value */
+    double* grad;             /* DEVICE, n x state_dim, or NULL: each
+                                 subsystem's gradient at its components */
+    double* u_star;           /* DEVICE, n x control_dim, or NULL */
+    const double* u_perf;     /* DEVICE, n x control_dim, or NULL */
+    double* u_out;            /* DEVICE, n x control_dim, or NULL (needs
+                                 u_perf): per subsystem, its inputs from u_perf
+                                 where its own value >= level, else its u_star */
+    double level;
+} hjr_query_decomposed;
+
+/* hjr_safety_query per subsystem at its part of each state, then the
+ * minimum.  Components of the state and control vectors that belong to no
+ * subsystem are left untouched.  EINVAL (nothing enqueued) for nsub outside
+ * 1..16, an invalid subsystem, overlapping or out-of-range state components,
+ * controls past control_dim, or the conditions of hjr_safety_query.
+ * Asynchronous on o->stream (nsub + 1 kernel launches). */
+hjr_status hjr_safety_query_decomposed(int32_t nsub, const hjr_subsystem* subs,
+                                       const hjr_query_decomposed* q, const hjr_opts* o);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of safe-set update requests (a request is a  */

@@ -136,10 +136,12 @@ def tune(problems, dtypes=("f32",), steps=64, log=print):
 
 
 def default_problems():
-    """The grid classes of the workloads: 2-D 51^2..201^2 and 4-D 21^4..61^4."""
+    """The grid classes of the workloads: 2-D 51^2..201^2 and 4-D 21^4..61^4,
+    and the 10-D model's x-subsystem at 21^4..61^4."""
     from . import workloads as W
     return ([W.quad_z2d(n, 0.5, f"z{n}") for n in (51, 101, 151, 201)] +
-            [W.quad_x4d(n, 0.5, f"x{n}") for n in (21, 31, 41, 51, 61)])
+            [W.quad_x4d(n, 0.5, f"x{n}") for n in (21, 31, 41, 51, 61)] +
+            [W.quad_x4dv(n, 0.3, f"xv{n}") for n in (21, 41, 61)])
 
 
 def main():

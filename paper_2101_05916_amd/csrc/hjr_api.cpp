@@ -522,37 +522,58 @@ hjr_status hjr_solve_batch(int32_t n, const hjr_problem* probs, const hjr_opts* 
     }
 }
 
+namespace {
+
+// Query arguments of one model and grid (state, value and control layouts
+// left to the caller).
+QueryArgs query_args(const hjr_dyn& dyn, const hjr_grid& grid, int order)
+{
+    QueryArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.kind = dyn.kind;
+    A.ndim = grid.ndim;
+    A.order = order;
+    A.nctrl = dyn.kind == HJR_DI2X2 ? 2 : 1;
+    int64_t st = 1;
+    for (int a = grid.ndim - 1; a >= 0; a--) {
+        A.n[a] = grid.n[a];
+        A.stride[a] = st;
+        st *= grid.n[a];
+        A.lo[a] = grid.lo[a];
+        A.hi[a] = grid.hi[a];
+        A.h[a] = (grid.hi[a] - grid.lo[a]) / (double)(grid.n[a] - 1);
+        A.hih[a] = 0.5 / A.h[a];
+    }
+    for (int i = 0; i < 16; i++) A.par[i] = dyn.p[i];
+    return A;
+}
+
+bool query_opts_valid(const hjr_opts& op)
+{
+    return (op.dtype == HJR_F32 || op.dtype == HJR_F64) && (op.order == 1 || op.order == 2);
+}
+
+}  // namespace
+
 hjr_status hjr_safety_query(const hjr_dyn* dyn, const hjr_grid* grid, const void* V,
                             const hjr_query* q, const hjr_opts* o)
 {
     const hjr_opts op = resolve(o);
     if (!dyn || !grid || !q) return HJR_EINVAL;
-    if (op.dtype != HJR_F32 && op.dtype != HJR_F64) return HJR_EINVAL;
-    if (op.order != 1 && op.order != 2) return HJR_EINVAL;
+    if (!query_opts_valid(op)) return HJR_EINVAL;
     if (!grid_valid(*grid) || !dyn_valid(*dyn, *grid)) return HJR_EINVAL;
     if (q->n < 0 || std::isnan(q->level)) return HJR_EINVAL;
     if (q->u_out && !q->u_perf) return HJR_EINVAL;
     if (q->n == 0) return HJR_OK;
     if (!q->x || !V) return HJR_EINVAL;
-    QueryArgs A;
-    std::memset(&A, 0, sizeof(A));
-    A.kind = dyn->kind;
-    A.ndim = grid->ndim;
-    A.order = op.order;
-    A.nctrl = dyn->kind == HJR_DI2X2 ? 2 : 1;
-    int64_t st = 1;
-    for (int a = grid->ndim - 1; a >= 0; a--) {
-        A.n[a] = grid->n[a];
-        A.stride[a] = st;
-        st *= grid->n[a];
-        A.lo[a] = grid->lo[a];
-        A.hi[a] = grid->hi[a];
-        A.h[a] = (grid->hi[a] - grid->lo[a]) / (double)(grid->n[a] - 1);
-        A.hih[a] = 0.5 / A.h[a];
-    }
-    for (int i = 0; i < 16; i++) A.par[i] = dyn->p[i];
+    QueryArgs A = query_args(*dyn, *grid, op.order);
     A.nq = q->n;
     A.x = q->x;
+    A.x_stride = grid->ndim;
+    for (int a = 0; a < 4; a++) A.x_map[a] = a;
+    A.u_stride = A.nctrl;
+    A.u_offset = 0;
+    A.v_stride = 1;
     A.value = q->value;
     A.grad = q->grad;
     A.u_star = q->u_star;
@@ -560,6 +581,54 @@ hjr_status hjr_safety_query(const hjr_dyn* dyn, const hjr_grid* grid, const void
     A.u_out = q->u_out;
     A.level = q->level;
     if (launch_query((hipStream_t)op.stream, op.dtype, A, V) != hipSuccess) return HJR_EDEVICE;
+    return HJR_OK;
+}
+
+hjr_status hjr_safety_query_decomposed(int32_t nsub, const hjr_subsystem* subs,
+                                       const hjr_query_decomposed* q, const hjr_opts* o)
+{
+    const hjr_opts op = resolve(o);
+    if (nsub < 1 || nsub > 16 || !subs || !q) return HJR_EINVAL;
+    if (!query_opts_valid(op)) return HJR_EINVAL;
+    if (q->n < 0 || std::isnan(q->level)) return HJR_EINVAL;
+    if (q->state_dim < 1 || q->control_dim < 0) return HJR_EINVAL;
+    if (q->u_out && !q->u_perf) return HJR_EINVAL;
+    uint32_t seen = 0;  // each full-state component belongs to one subsystem at most
+    for (int s = 0; s < nsub; s++) {
+        const hjr_subsystem& sb = subs[s];
+        if (!grid_valid(sb.grid) || !dyn_valid(sb.dyn, sb.grid)) return HJR_EINVAL;
+        for (int a = 0; a < sb.grid.ndim; a++) {
+            const int c = sb.state_index[a];
+            if (c < 0 || c >= q->state_dim || c >= 32 || (seen >> c & 1u)) return HJR_EINVAL;
+            seen |= 1u << c;
+        }
+        const int m = sb.dyn.kind == HJR_DI2X2 ? 2 : 1;
+        if (sb.control_index < 0 || sb.control_index + m > q->control_dim) return HJR_EINVAL;
+        if (q->n > 0 && !sb.V) return HJR_EINVAL;
+    }
+    if (q->n == 0) return HJR_OK;
+    if (!q->x || !q->sub_value) return HJR_EINVAL;
+    hipStream_t st = (hipStream_t)op.stream;
+    for (int s = 0; s < nsub; s++) {
+        const hjr_subsystem& sb = subs[s];
+        QueryArgs A = query_args(sb.dyn, sb.grid, op.order);
+        A.nq = q->n;
+        A.x = q->x;
+        A.x_stride = q->state_dim;
+        for (int a = 0; a < 4; a++) A.x_map[a] = a < sb.grid.ndim ? sb.state_index[a] : 0;
+        A.u_stride = q->control_dim;
+        A.u_offset = sb.control_index;
+        A.v_stride = nsub;
+        A.value = q->sub_value + s;
+        A.grad = q->grad;
+        A.u_star = q->u_star;
+        A.u_perf = q->u_perf;
+        A.u_out = q->u_out;
+        A.level = q->level;
+        if (launch_query(st, op.dtype, A, sb.V) != hipSuccess) return HJR_EDEVICE;
+    }
+    if (launch_query_min(st, q->sub_value, nsub, q->n, q->value, q->active) != hipSuccess)
+        return HJR_EDEVICE;
     return HJR_OK;
 }
 

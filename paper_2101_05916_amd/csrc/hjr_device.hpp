@@ -64,23 +64,31 @@ enum TilePath : int32_t { kPathFlat = 0, kPathPlaneS = 1, kPathPlaneL = 2 };
 // LDS are sized for its tile code alone; a chunk launches one kernel per
 // family present.  Plane families are (model, row stride, ENO order), and
 // (model, row stride) with ENO2 for problems with per-node disturbance
-// bounds (the "F" families; such problems with first-order derivatives take
-// flat tiles).
+// bounds (the "F" families).  Plane problems without a family of their own
+// (first-order derivatives with per-node bounds or on the 10-D model's
+// x-subsystem) take flat tiles.
 enum Family : int32_t {
     kFamFlat = 0,
     kFamZ2dS2, kFamZ2dL2, kFamX4dS2, kFamX4dL2,
     kFamZ2dS1, kFamZ2dL1, kFamX4dS1, kFamX4dL1,
     kFamZ2dS2F, kFamZ2dL2F, kFamX4dS2F, kFamX4dL2F,
+    kFamXvS2, kFamXvL2, kFamXvS2F, kFamXvL2F,  // QUAD_X4DV
     kNumFam
 };
 
-// Plane families come in groups of four: (Z2D, narrow), (Z2D, wide),
-// (X4D, narrow), (X4D, wide).
-__host__ __device__ constexpr int fam_slot(int f) { return (f - 1) & 3; }
+// Model of a plane family (HJR_QUAD_Z2D, HJR_QUAD_X4D, HJR_QUAD_X4DV; -1 flat).
+__host__ __device__ constexpr int fam_model(int f)
+{
+    return f == kFamFlat ? -1
+         : f >= kFamXvS2 ? HJR_QUAD_X4DV
+         : (((f - 1) & 3) >= 2 ? HJR_QUAD_X4D : HJR_QUAD_Z2D);
+}
 
+// Narrow plane (row stride 72) or wide (208): within each group of four
+// (Z2D S, Z2D L, X4D S, X4D L) and in the QUAD_X4DV group (S, L, S, L).
 __host__ __device__ constexpr int fam_rs(int f)
 {
-    return f == kFamFlat ? 0 : ((fam_slot(f) & 1) ? kRowStrideL : kRowStrideS);
+    return f == kFamFlat ? 0 : (((f - 1) & 1) ? kRowStrideL : kRowStrideS);
 }
 
 __host__ __device__ constexpr int fam_order(int f)
@@ -88,14 +96,14 @@ __host__ __device__ constexpr int fam_order(int f)
     return (f >= kFamZ2dS1 && f <= kFamX4dL1) ? 1 : 2;
 }
 
-__host__ __device__ constexpr bool fam_x4d(int f)
+__host__ __device__ constexpr bool fam_x4d(int f)  // a 4-D model
 {
-    return f != kFamFlat && fam_slot(f) >= 2;
+    return fam_model(f) == HJR_QUAD_X4D || fam_model(f) == HJR_QUAD_X4DV;
 }
 
 __host__ __device__ constexpr bool fam_field(int f)
 {
-    return f >= kFamZ2dS2F;
+    return (f >= kFamZ2dS2F && f <= kFamX4dL2F) || f >= kFamXvS2F;
 }
 
 // LDS elements of a plane block of row stride rs (0 for flat tiles).
@@ -163,12 +171,14 @@ struct ProbDesc {
 typedef const HJR_CONST ProbDesc PDesc;
 
 // Family of a problem's tiles (its model, tile path, ENO order and whether
-// it has a disturbance field; the host sends a field with first-order
-// derivatives to flat tiles).
+// it has a disturbance field); the host sends the problems without a plane
+// family to flat tiles.
 inline int family_of(const ProbDesc& P)
 {
     if (P.path == kPathFlat) return kFamFlat;
-    const bool narrow = P.path == kPathPlaneS, x4 = P.kind == HJR_QUAD_X4D;
+    const bool narrow = P.path == kPathPlaneS;
+    if (P.kind == HJR_QUAD_X4DV) return (P.dfield ? kFamXvS2F : kFamXvS2) + (narrow ? 0 : 1);
+    const bool x4 = P.kind == HJR_QUAD_X4D;
     // first of the group Z2D S, Z2D L, X4D S, X4D L
     const int base = P.dfield ? kFamZ2dS2F : (P.order == 1 ? kFamZ2dS1 : kFamZ2dS2);
     return base + (x4 ? 2 : 0) + (narrow ? 0 : 1);

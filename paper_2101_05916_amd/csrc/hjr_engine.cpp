@@ -48,6 +48,7 @@ int dyn_dim(int kind)
     switch (kind) {
     case HJR_QUAD_Z2D: return 2;
     case HJR_QUAD_X4D: return 4;
+    case HJR_QUAD_X4DV: return 4;
     case HJR_DI2X2: return 4;
     default: return 0;
     }
@@ -58,6 +59,7 @@ int dyn_channels(int kind)
     switch (kind) {
     case HJR_QUAD_Z2D: return 1;
     case HJR_QUAD_X4D: return 1;
+    case HJR_QUAD_X4DV: return 1;
     case HJR_DI2X2: return 2;
     default: return 0;
     }
@@ -70,8 +72,9 @@ bool dyn_valid(const hjr_dyn& d, const hjr_grid& g)
     for (int i = 0; i < 16; i++)
         if (!std::isfinite(d.p[i])) return false;
     if (d.kind == HJR_QUAD_Z2D && !(d.p[2] <= d.p[3])) return false;
-    if (d.kind == HJR_QUAD_X4D && !(d.p[4] >= 0.0)) return false;
-    if (d.kind == HJR_QUAD_X4D) {
+    const bool x4 = d.kind == HJR_QUAD_X4D || d.kind == HJR_QUAD_X4DV;
+    if (x4 && !(d.p[4] >= 0.0)) return false;
+    if (x4) {
         // tan(theta) must stay finite on the grid
         const double half_pi = 1.5707963267948966;
         if (!(g.lo[2] > -half_pi && g.hi[2] < half_pi)) return false;
@@ -322,19 +325,21 @@ void Engine::fill_desc(const Job* j, ProbDesc& P) const
         hc[4] = (std::max(ku_lo, ku_hi) - p[1]) * P.hih[1];
         hc[5] = (std::min(ku_lo, ku_hi) - p[1]) * P.hih[1];
         hc[6] = P.hih[1];
-    } else if (P.kind == HJR_QUAD_X4D) {
+    } else if (P.kind == HJR_QUAD_X4D || P.kind == HJR_QUAD_X4DV) {
         const double g_ = p[0], d1 = p[1], d0 = p[2], n0 = p[3], sm = p[4];
+        // the disturbance enters x' (QUAD_X4D) or vx' (QUAD_X4DV)
+        const double hd = P.kind == HJR_QUAD_X4DV ? P.hih[1] : P.hih[0];
         hc[0] = P.hih[0] * P.lo[1];
         hc[1] = P.hih[0] * P.h[1];
-        hc[2] = P.dlo[0] * P.hih[0];
-        hc[3] = P.dhi[0] * P.hih[0];
+        hc[2] = P.dlo[0] * hd;
+        hc[3] = P.dhi[0] * hd;
         hc[4] = P.hih[2] * (P.lo[3] - d1 * P.lo[2]);
         hc[5] = P.hih[2] * P.h[3];
         hc[6] = P.hih[2] * d1 * P.h[2];
         hc[7] = d0 * P.hih[3] * P.lo[2];
         hc[8] = d0 * P.hih[3] * P.h[2];
         hc[9] = n0 * sm * P.hih[3];
-        hc[10] = P.hih[0];  // scales a per-node disturbance bound
+        hc[10] = hd;  // scales a per-node disturbance bound
         (void)g_;
     }
     for (int i = 0; i < 16; i++) P.hc_f[i] = (float)P.hc_d[i];
@@ -342,10 +347,11 @@ void Engine::fill_desc(const Job* j, ProbDesc& P) const
     // else flat tiles of kTile consecutive nodes
     P.path = kPathFlat;
     P.ntiles = (P.N + kTile - 1) / kTile;
-    // (per-node disturbance boxes have plane families for ENO2 only)
-    const bool plane_kind = (P.kind == HJR_QUAD_Z2D || P.kind == HJR_QUAD_X4D) &&
-                            !(cfg_.flags & HJR_FLAG_FLAT_TILES) &&
-                            !(P.dfield && P.order != 2);
+    // (per-node disturbance boxes and QUAD_X4DV have plane families for ENO2 only)
+    const bool plane_kind =
+        (P.kind == HJR_QUAD_Z2D || P.kind == HJR_QUAD_X4D || P.kind == HJR_QUAD_X4DV) &&
+        !(cfg_.flags & HJR_FLAG_FLAT_TILES) &&
+        !((P.dfield || P.kind == HJR_QUAD_X4DV) && P.order != 2);
     // plane tiles address with 32-bit byte offsets
     const bool fits32 = (double)P.N * (double)elem_size(cfg_.dtype) < 4294967296.0;
     if (plane_kind && fits32 && (D == 2 || D == 4)) {

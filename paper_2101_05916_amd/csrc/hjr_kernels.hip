@@ -207,11 +207,13 @@ __device__ void dyn_f(const ProbDesc& P, const double* x, int vu, int vd, const 
         f[1] = p[0] * u - p[1] + d;
         break;
     }
-    case HJR_QUAD_X4D: {
+    case HJR_QUAD_X4D:
+    case HJR_QUAD_X4DV: {
         const double S = (vu & 1) ? p[4] : -p[4];
         const double d = (vd & 1) ? dh[0] : dl[0];
-        f[0] = x[1] + d;
-        f[1] = p[0] * tan(x[2]);
+        const bool vdist = P.kind == HJR_QUAD_X4DV;  // disturbance on vx' instead of x'
+        f[0] = x[1] + (vdist ? 0.0 : d);
+        f[1] = p[0] * tan(x[2]) + (vdist ? d : 0.0);
         f[2] = -p[1] * x[2] + x[3];
         f[3] = -p[2] * x[2] + p[3] * S;
         break;
@@ -292,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(ProbDesc P, ProbState* st)
         st->dt = P.cfl / s;
         st->dt_f = (float)st->dt;
     }
-    if (P.kind == HJR_QUAD_X4D && P.table) {
+    if ((P.kind == HJR_QUAD_X4D || P.kind == HJR_QUAD_X4DV) && P.table) {
         T* tab = (T*)P.table;
         for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < P.n[2]; j += gridDim.x * blockDim.x)
             tab[j] = (T)(P.par[0] * tan(P.lo[2] + (double)j * P.h[2]) * P.hih[1]);
@@ -503,6 +505,10 @@ static hipError_t launch_stage_t(hipStream_t s, int fam, const ChunkArgs& a, int
     case kFamZ2dL2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamZ2dL2F>), g, b, 0, s, a); break;
     case kFamX4dS2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dS2F>), g, b, 0, s, a); break;
     case kFamX4dL2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dL2F>), g, b, 0, s, a); break;
+    case kFamXvS2: hipLaunchKernelGGL((k_stage<T, STAGE, kFamXvS2>), g, b, 0, s, a); break;
+    case kFamXvL2: hipLaunchKernelGGL((k_stage<T, STAGE, kFamXvL2>), g, b, 0, s, a); break;
+    case kFamXvS2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamXvS2F>), g, b, 0, s, a); break;
+    case kFamXvL2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamXvL2F>), g, b, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -637,7 +643,11 @@ static const void* stage_kernel(int fam)
     case kFamZ2dS2F: return (const void*)k_stage<T, STAGE, kFamZ2dS2F>;
     case kFamZ2dL2F: return (const void*)k_stage<T, STAGE, kFamZ2dL2F>;
     case kFamX4dS2F: return (const void*)k_stage<T, STAGE, kFamX4dS2F>;
-    default: return (const void*)k_stage<T, STAGE, kFamX4dL2F>;
+    case kFamX4dL2F: return (const void*)k_stage<T, STAGE, kFamX4dL2F>;
+    case kFamXvS2: return (const void*)k_stage<T, STAGE, kFamXvS2>;
+    case kFamXvL2: return (const void*)k_stage<T, STAGE, kFamXvL2>;
+    case kFamXvS2F: return (const void*)k_stage<T, STAGE, kFamXvS2F>;
+    default: return (const void*)k_stage<T, STAGE, kFamXvL2F>;
     }
 }
 

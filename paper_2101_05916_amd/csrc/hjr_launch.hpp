@@ -54,15 +54,28 @@ struct QueryArgs {
     double hih[4];           // 0.5 / h
     double par[16];
     int64_t nq;              // states
-    const double* x;         // nq x ndim
-    double* value;           // nq, or null
-    double* grad;            // nq x ndim, or null
-    double* u_star;          // nq x nctrl, or null
-    const double* u_perf;    // nq x nctrl, or null
-    double* u_out;           // nq x nctrl, or null (needs u_perf)
+    // state i's axis a is x[i * x_stride + x_map[a]]; its gradient goes to
+    // the same place of grad
+    const double* x;
+    int32_t x_stride;
+    int32_t x_map[4];
+    int32_t u_stride;        // controls of state i start at i * u_stride + u_offset
+    int32_t u_offset;
+    int32_t pad;
+    int64_t v_stride;        // value of state i at value[i * v_stride]
+    double* value;           // or null
+    double* grad;            // or null
+    double* u_star;          // or null
+    const double* u_perf;    // or null
+    double* u_out;           // or null (needs u_perf)
     double level;
 };
 hipError_t launch_query(hipStream_t s, int dtype, const QueryArgs& A, const void* V);
+
+// Decomposed value: value[i] = min over s of sub[i * nsub + s] (NaN if any is
+// NaN), active[i] = the first s attaining it (-1 then); active may be null.
+hipError_t launch_query_min(hipStream_t s, const double* sub, int32_t nsub, int64_t n,
+                            double* value, int32_t* active);
 
 // Workgroups of a stage kernel that fit on one compute unit.
 int stage_blocks_per_cu(int dtype, int stage, int fam);

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs A, const T* __restri
         double t[D];
         bool inside = live;
         for (int b = 0; b < D; b++) {
-            const double xb = live ? A.x[i * D + b] : 0.0;
+            const double xb = live ? A.x[i * A.x_stride + A.x_map[b]] : 0.0;
             if (!(xb >= A.lo[b] && xb <= A.hi[b])) inside = false;
             const double s = inside ? (xb - A.lo[b]) / A.h[b] : 0.0;
             const int j = min(max((int)floor(s), 0), A.n[b] - 2);
@@ -108,14 +108,20 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs A, const T* __restri
             for (int b = 0; b < D; b++) g[b] = NAN;
         }
         if (!live) continue;
-        if (r < D && A.grad) A.grad[i * D + r] = inside ? ga : NAN;
+        if (r < D && A.grad) {
+            int mr = A.x_map[0];
+#pragma unroll
+            for (int b = 1; b < D; b++) mr = b == r ? A.x_map[b] : mr;
+            A.grad[i * A.x_stride + mr] = inside ? ga : NAN;
+        }
         if (r != 0) continue;
         double u[2] = {NAN, NAN};
         if (inside) {
             const double* p = A.par;
             switch (A.kind) {
             case HJR_QUAD_Z2D: u[0] = (p[0] * g[1] >= 0.0) ? p[3] : p[2]; break;
-            case HJR_QUAD_X4D: u[0] = (p[3] * g[3 % D] >= 0.0) ? p[4] : -p[4]; break;
+            case HJR_QUAD_X4D:
+            case HJR_QUAD_X4DV: u[0] = (p[3] * g[3 % D] >= 0.0) ? p[4] : -p[4]; break;
             case HJR_DI2X2: {
                 // the velocity axes of the two copies (selects, not a
                 // run-time index into g)
@@ -133,19 +139,51 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs A, const T* __restri
             default: break;
             }
         }
-        if (A.value) A.value[i] = value;
+        if (A.value) A.value[i * A.v_stride] = value;
         const int m = A.nctrl;  // 1 or 2
+        const int64_t u0 = i * A.u_stride + A.u_offset;
         const bool keep = value >= A.level;  // false for NaN: outside the box
 #pragma unroll
         for (int k = 0; k < 2; k++) {
             if (k >= m) break;
-            if (A.u_star) A.u_star[i * m + k] = u[k];
-            if (A.u_out) A.u_out[i * m + k] = keep ? A.u_perf[i * m + k] : u[k];
+            if (A.u_star) A.u_star[u0 + k] = u[k];
+            if (A.u_out) A.u_out[u0 + k] = keep ? A.u_perf[u0 + k] : u[k];
         }
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_query_min(const double* __restrict__ sub, int32_t nsub,
+                                                    int64_t n, double* value, int32_t* active)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double best = INFINITY;
+        int arg = -1;
+        bool nan = false;
+        for (int s = 0; s < nsub; s++) {
+            const double v = sub[i * nsub + s];
+            nan = nan || isnan(v);
+            if (v < best) {
+                best = v;
+                arg = s;
+            }
+        }
+        if (value) value[i] = nan ? NAN : best;
+        if (active) active[i] = nan ? -1 : arg;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_query_min(hipStream_t s, const double* sub, int32_t nsub, int64_t n,
+                            double* value, int32_t* active)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + kBlock - 1) / kBlock;
+    const int g = (int)(blocks < 65536 ? blocks : 65536);
+    hipLaunchKernelGGL(k_query_min, dim3(g), dim3(kBlock), 0, s, sub, nsub, n, value, active);
+    return hipGetLastError();
+}
 
 hipError_t launch_query(hipStream_t s, int dtype, const QueryArgs& A, const void* V)
 {

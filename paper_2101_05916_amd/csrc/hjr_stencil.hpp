@@ -225,7 +225,9 @@ struct HamZ2DF {
 // omega' = -d0 theta + n0 S.  hc = {hih0*lo1, hih0*h1, dlo*hih0, dhi*hih0,
 // hih2*(lo3 - d1 lo2), hih2*h3, hih2*d1*h2, d0*hih3*lo2, d0*hih3*h2,
 // n0*smax*hih3}; table[j2] = g tan(theta_j2) * hih1.
-template <typename T>
+// VD: the 10-D model's form, the disturbance on the velocity rate
+// (x' = vx, vx' = g tan(theta) + d); then hc[2], hc[3] = dlo*hih1, dhi*hih1.
+template <typename T, bool VD = false>
 struct HamX4D {
     T c0, c1, dl, dh, A, B, C, D, E, n0s;
     const T* gts;
@@ -251,8 +253,11 @@ struct HamX4D {
         const T cvx = c0 + (T)j1 * c1;                   // (0.5/h0) vx
         const T tw = A + (T)j3 * B - (T)j2 * C;          // (0.5/h2)(omega - d1 theta)
         const T t3 = D + (T)j2 * E;                      // (0.5/h3) d0 theta
-        const T s0 = sum[0];
-        return s0 * (cvx + (s0 >= T(0) ? dl : dh)) + sum[1] * g + sum[2] * tw - sum[3] * t3 +
+        const T s0 = sum[0], s1 = sum[1];
+        if (VD)
+            return s0 * cvx + s1 * (g + (s1 >= T(0) ? dl : dh)) + sum[2] * tw - sum[3] * t3 +
+                   n0s * fabs(sum[3]);
+        return s0 * (cvx + (s0 >= T(0) ? dl : dh)) + s1 * g + sum[2] * tw - sum[3] * t3 +
                n0s * fabs(sum[3]);
     }
     __device__ __forceinline__ T operator()(const T* sum, int j0, int j1, int j2, int j3) const
@@ -265,9 +270,9 @@ struct HamX4D {
     __device__ __forceinline__ Node node_i(int j2, int64_t) const { return row_coef(j2); }
 };
 
-// The x-subsystem with a per-node disturbance box on x' (field layout as for
-// HamZ2DF); hc[10] = hih0.
-template <typename T>
+// The x-subsystem with a per-node disturbance box (field layout as for
+// HamZ2DF) on x', hc[10] = hih0, or with VD on vx', hc[10] = hih1.
+template <typename T, bool VD = false>
 struct HamX4DF {
     T c0, c1, h0, A, B, C, D, E, n0s;
     const T* gts;
@@ -305,8 +310,11 @@ struct HamX4DF {
         const T cvx = c0 + (T)j1 * c1;
         const T tw = A + (T)j3 * B - (T)j2 * C;
         const T t3 = D + (T)j2 * E;
-        const T s0 = sum[0];
-        return s0 * (cvx + (s0 >= T(0) ? nd.dl : nd.dh) * h0) + sum[1] * nd.g + sum[2] * tw -
+        const T s0 = sum[0], s1 = sum[1];
+        if (VD)
+            return s0 * cvx + s1 * (nd.g + (s1 >= T(0) ? nd.dl : nd.dh) * h0) + sum[2] * tw -
+                   sum[3] * t3 + n0s * fabs(sum[3]);
+        return s0 * (cvx + (s0 >= T(0) ? nd.dl : nd.dh) * h0) + s1 * nd.g + sum[2] * tw -
                sum[3] * t3 + n0s * fabs(sum[3]);
     }
 };
@@ -687,6 +695,7 @@ __device__ __forceinline__ uint64_t run_tile(PDesc& P, PState& S, uint32_t tile,
             switch (P.kind) {
             case HJR_QUAD_Z2D: return tile_flat<T, 2, HamZ2DF<T>, STAGE>(P, S, tile);
             case HJR_QUAD_X4D: return tile_flat<T, 4, HamX4DF<T>, STAGE>(P, S, tile);
+            case HJR_QUAD_X4DV: return tile_flat<T, 4, HamX4DF<T, true>, STAGE>(P, S, tile);
             case HJR_DI2X2: return tile_flat<T, 4, HamDI2X2<T, true>, STAGE>(P, S, tile);
             default: return 0;
             }
@@ -694,23 +703,27 @@ __device__ __forceinline__ uint64_t run_tile(PDesc& P, PState& S, uint32_t tile,
         switch (P.kind) {
         case HJR_QUAD_Z2D: return tile_flat<T, 2, HamZ2D<T>, STAGE>(P, S, tile);
         case HJR_QUAD_X4D: return tile_flat<T, 4, HamX4D<T>, STAGE>(P, S, tile);
+        case HJR_QUAD_X4DV: return tile_flat<T, 4, HamX4D<T, true>, STAGE>(P, S, tile);
         case HJR_DI2X2: return tile_flat<T, 4, HamDI2X2<T>, STAGE>(P, S, tile);
         default: return 0;
         }
-    } else if constexpr (fam_field(FAM)) {
-        // per-node disturbance boxes: the element tile, both stages
-        constexpr int RS = fam_rs(FAM);
-        if constexpr (fam_x4d(FAM))
-            return tile_plane<T, 4, HamX4DF<T>, STAGE, RS, 2>(P, S, tile, lds);
-        else
-            return tile_plane<T, 2, HamZ2DF<T>, STAGE, RS, 2>(P, S, tile, lds);
     } else {
         constexpr int RS = fam_rs(FAM);
         constexpr int ORDER = fam_order(FAM);
-        if constexpr (fam_x4d(FAM))
-            return tile_plane<T, 4, HamX4D<T>, STAGE, RS, ORDER>(P, S, tile, lds);
-        else
-            return tile_plane<T, 2, HamZ2D<T>, STAGE, RS, ORDER>(P, S, tile, lds);
+        constexpr int M = fam_model(FAM);
+        constexpr bool VD = M == HJR_QUAD_X4DV;
+        if constexpr (fam_field(FAM)) {
+            // per-node disturbance boxes
+            if constexpr (M == HJR_QUAD_Z2D)
+                return tile_plane<T, 2, HamZ2DF<T>, STAGE, RS, 2>(P, S, tile, lds);
+            else
+                return tile_plane<T, 4, HamX4DF<T, VD>, STAGE, RS, 2>(P, S, tile, lds);
+        } else {
+            if constexpr (M == HJR_QUAD_Z2D)
+                return tile_plane<T, 2, HamZ2D<T>, STAGE, RS, ORDER>(P, S, tile, lds);
+            else
+                return tile_plane<T, 4, HamX4D<T, VD>, STAGE, RS, ORDER>(P, S, tile, lds);
+        }
     }
 }
 

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhjr.so")
 
 OK, EINVAL, ENOMEM, NOT_CONVERGED, EDEVICE, EBUSY, ENOTFOUND = range(7)
 F32, F64 = 0, 1
-QUAD_Z2D, QUAD_X4D, DI2X2 = 0, 1, 2
+QUAD_Z2D, QUAD_X4D, DI2X2, QUAD_X4DV = 0, 1, 2, 3
 FLAG_NO_GRAPH, FLAG_NO_PIPELINE, FLAG_PROFILE, FLAG_FLAT_TILES = 1, 2, 4, 8
 
 EXPORTS = (
@@ -26,7 +26,7 @@ EXPORTS = (
     "hjr_interp", "hjr_refine_mask", "hjr_solve_levels", "hjr_batch_workspace_bytes",
     "hjr_solve_batch", "hjr_server_create", "hjr_server_submit", "hjr_server_poll",
     "hjr_server_wait", "hjr_server_read_value", "hjr_server_memory", "hjr_server_destroy",
-    "hjr_solve_field", "hjr_safety_query",
+    "hjr_solve_field", "hjr_safety_query", "hjr_safety_query_decomposed",
 )
 
 
@@ -83,6 +83,18 @@ class Query(C.Structure):
     _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("value", C.c_void_p),
                 ("grad", C.c_void_p), ("u_star", C.c_void_p), ("u_perf", C.c_void_p),
                 ("u_out", C.c_void_p), ("level", C.c_double)]
+
+
+class Subsystem(C.Structure):
+    _fields_ = [("dyn", Dyn), ("grid", Grid), ("V", C.c_void_p), ("state_index", C.c_int32 * 4),
+                ("control_index", C.c_int32), ("reserved", C.c_int32)]
+
+
+class QueryDecomposed(C.Structure):
+    _fields_ = [("n", C.c_int64), ("state_dim", C.c_int32), ("control_dim", C.c_int32),
+                ("x", C.c_void_p), ("sub_value", C.c_void_p), ("value", C.c_void_p),
+                ("active", C.c_void_p), ("grad", C.c_void_p), ("u_star", C.c_void_p),
+                ("u_perf", C.c_void_p), ("u_out", C.c_void_p), ("level", C.c_double)]
 
 
 class ServerCfg(C.Structure):
@@ -143,6 +155,8 @@ def lib() -> C.CDLL:
                                   C.c_void_p, C.c_double, P(Opts), P(C.c_void_p), P(Stats)]
     L.hjr_safety_query.restype = st
     L.hjr_safety_query.argtypes = [P(Dyn), P(Grid), C.c_void_p, P(Query), P(Opts)]
+    L.hjr_safety_query_decomposed.restype = st
+    L.hjr_safety_query_decomposed.argtypes = [C.c_int32, P(Subsystem), P(QueryDecomposed), P(Opts)]
     L.hjr_batch_workspace_bytes.restype = st
     L.hjr_batch_workspace_bytes.argtypes = [C.c_int32, P(Problem), P(Opts), P(C.c_size_t)]
     L.hjr_solve_batch.restype = st
@@ -544,6 +558,65 @@ def query(spec: Spec, V, X, *, order=2, u_perf=None, level=0.0, grad=True, u_sta
     dyn = make_dyn(spec.kind, spec.params)
     _raise(lib().hjr_safety_query(C.byref(dyn), C.byref(g_), _ptr(V), C.byref(q), C.byref(o)),
            "hjr_safety_query")
+    return res
+
+
+def query_decomposed(subsystems, X, *, control_dim=None, order=2, u_perf=None, level=0.0,
+                     stream=None, out=None):
+    """Decomposed safety query (hjr_safety_query_decomposed).  subsystems:
+    list of (spec, V, state_index, control_index); X: device float64 tensor
+    (n, state_dim).  Returns a dict of device tensors: sub_value (n, nsub),
+    value (n,), active (n,) int32, grad (n, state_dim), u_star (n,
+    control_dim) and, with u_perf, u_out."""
+    torch = _torch()
+    if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float64
+            and X.is_contiguous() and X.dim() == 2):
+        raise ValueError("X must be a contiguous CUDA float64 tensor (n, state_dim)")
+    n, dim = X.shape
+    ns = len(subsystems)
+    if control_dim is None:
+        control_dim = max(c + controls(sp.kind) for sp, _, _, c in subsystems)
+    arr = (Subsystem * ns)()
+    vdtype = None
+    for k, (sp, V, idx, c) in enumerate(subsystems):
+        _check_tensor(V, sp.size, V.dtype, f"V[{k}]")
+        if vdtype is not None and V.dtype != vdtype:
+            raise ValueError("every subsystem value must have the same dtype")
+        vdtype = V.dtype
+        arr[k].dyn = make_dyn(sp.kind, sp.params)
+        arr[k].grid = make_grid(sp.n, sp.lo, sp.hi)
+        arr[k].V = V.data_ptr()
+        for a, ci in enumerate(idx):
+            arr[k].state_index[a] = int(ci)
+        arr[k].control_index = int(c)
+    res = dict(out or {})
+    dev = X.device
+
+    def buf(name, shape, dt=torch.float64):
+        if name not in res:
+            res[name] = torch.empty(shape, dtype=dt, device=dev)
+        return res[name].data_ptr()
+
+    q = QueryDecomposed()
+    q.n = n
+    q.state_dim = dim
+    q.control_dim = control_dim
+    q.x = X.data_ptr()
+    q.sub_value = buf("sub_value", (n, ns))
+    q.value = buf("value", (n,))
+    q.active = buf("active", (n,), torch.int32)
+    q.grad = buf("grad", (n, dim))
+    q.u_star = buf("u_star", (n, control_dim))
+    if u_perf is not None:
+        if not (u_perf.is_cuda and u_perf.dtype == torch.float64 and u_perf.is_contiguous()
+                and u_perf.numel() == n * control_dim):
+            raise ValueError("u_perf must be a contiguous CUDA float64 tensor (n, control_dim)")
+        q.u_perf = u_perf.data_ptr()
+        q.u_out = buf("u_out", (n, control_dim))
+    q.level = float(level)
+    o = make_opts(vdtype, order, stream=stream)
+    _raise(lib().hjr_safety_query_decomposed(ns, arr, C.byref(q), C.byref(o)),
+           "hjr_safety_query_decomposed")
     return res
 
 

@@ -39,9 +39,10 @@ def test_struct_layouts_match_c():
 #include <stddef.h>
 #include "hjr.h"
 int main(void){
- printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hjr_grid), sizeof(hjr_dyn),
+ printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hjr_grid), sizeof(hjr_dyn),
    sizeof(hjr_dstb), sizeof(hjr_opts), sizeof(hjr_stats), sizeof(hjr_problem),
-   sizeof(hjr_server_cfg), sizeof(hjr_request), sizeof(hjr_reply), sizeof(hjr_query));
+   sizeof(hjr_server_cfg), sizeof(hjr_request), sizeof(hjr_reply), sizeof(hjr_query),
+   sizeof(hjr_subsystem), sizeof(hjr_query_decomposed));
  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(hjr_opts, flags),
    offsetof(hjr_stats, kernel_launches), offsetof(hjr_problem, tol), offsetof(hjr_request, cold),
    offsetof(hjr_problem, dfield), offsetof(hjr_request, dfield));
@@ -57,6 +58,7 @@ int main(void){
     want = [C.sizeof(hjr.Grid), C.sizeof(hjr.Dyn), C.sizeof(hjr.Dstb), C.sizeof(hjr.Opts),
             C.sizeof(hjr.Stats), C.sizeof(hjr.Problem), C.sizeof(hjr.ServerCfg),
             C.sizeof(hjr.Request), C.sizeof(hjr.Reply), C.sizeof(hjr.Query),
+            C.sizeof(hjr.Subsystem), C.sizeof(hjr.QueryDecomposed),
             hjr.Opts.flags.offset, hjr.Stats.kernel_launches.offset, hjr.Problem.tol.offset,
             hjr.Request.cold.offset, hjr.Problem.dfield.offset, hjr.Request.dfield.offset]
     assert got == want
@@ -206,6 +208,43 @@ def test_safety_query_rejects_invalid_without_device():
     bad = hjr.make_dyn(hjr.QUAD_X4D, (9.81, 8.0, 10.0, 10.0, 0.35))  # 4-D model on a 2-D grid
     assert L.hjr_safety_query(C.byref(bad), C.byref(g), V, C.byref(q), C.byref(o)) == hjr.EINVAL
     assert L.hjr_safety_query(C.byref(dyn), C.byref(g), None, C.byref(q), C.byref(o)) == hjr.EINVAL
+
+
+def test_decomposed_query_rejects_invalid_without_device():
+    L = hjr.lib()
+    zx = hjr.make_dyn(hjr.QUAD_X4DV, (9.81, 8.0, 10.0, 10.0, 0.244))
+    zz = hjr.make_dyn(hjr.QUAD_Z2D, (1.0, 9.81, 5.9, 13.7))
+    subs = (hjr.Subsystem * 2)()
+    subs[0].dyn = zx
+    subs[0].grid = hjr.make_grid((5, 5, 5, 5), (-3, -4, -0.5, -4), (3, 4, 0.5, 4))
+    subs[0].V = 0x1000
+    for a in range(4):
+        subs[0].state_index[a] = a
+    subs[0].control_index = 0
+    subs[1].dyn = zz
+    subs[1].grid = hjr.make_grid((9, 9), (0, -4.5), (3.2, 4.5))
+    subs[1].V = 0x2000
+    subs[1].state_index[0], subs[1].state_index[1] = 4, 5
+    subs[1].control_index = 1
+    q = hjr.QueryDecomposed()
+    q.n, q.state_dim, q.control_dim = 0, 6, 2
+    o = hjr.Opts()
+    L.hjr_opts_default(C.byref(o))
+    assert L.hjr_safety_query_decomposed(2, subs, C.byref(q), C.byref(o)) == hjr.OK  # nothing to do
+    q.n = 3
+    q.x = 0x3000
+    assert L.hjr_safety_query_decomposed(2, subs, C.byref(q), C.byref(o)) == hjr.EINVAL  # no sub_value
+    q.sub_value = 0x4000
+    q.state_dim = 5  # component 5 out of range
+    assert L.hjr_safety_query_decomposed(2, subs, C.byref(q), C.byref(o)) == hjr.EINVAL
+    q.state_dim = 6
+    subs[1].state_index[0] = 3  # overlaps the first subsystem
+    assert L.hjr_safety_query_decomposed(2, subs, C.byref(q), C.byref(o)) == hjr.EINVAL
+    subs[1].state_index[0] = 4
+    q.control_dim = 1  # second subsystem's control past the vector
+    assert L.hjr_safety_query_decomposed(2, subs, C.byref(q), C.byref(o)) == hjr.EINVAL
+    q.control_dim = 2
+    assert L.hjr_safety_query_decomposed(0, subs, C.byref(q), C.byref(o)) == hjr.EINVAL
 
 
 def test_batch_and_server_reject_invalid():
