@@ -787,3 +787,111 @@ int orc_query_decomposed(int nsub, const orc_dyn* dyns, const orc_grid* grids,
     *active = status == ORC_OK ? arg : -1;
     return status;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Localized updates (Sec. VI: localized warm starting)                     */
+/* ------------------------------------------------------------------------ */
+
+int64_t orc_band_mask(const orc_grid* g, const double* V, int k, uint8_t* node_mask)
+{
+    int D = g->ndim;
+    int64_t N = grid_size(g);
+    int64_t Nc = 1;
+    int nc[4];
+    for (int a = 0; a < D; a++) {
+        nc[a] = g->n[a] - 1;
+        Nc *= nc[a];
+    }
+    uint8_t* cells = (uint8_t*)malloc((size_t)Nc);
+    orc_refine_mask(g, V, cells);
+    int64_t count = 0;
+    int j[4], c[4];
+    for (int64_t i = 0; i < N; i++) {
+        unflatten(g, i, j);
+        int hit = 0;
+        /* every cell c with max_a dist(j_a, [c_a, c_a + 1]) <= k */
+        int lo[4], hi[4];
+        for (int a = 0; a < D; a++) {
+            lo[a] = j[a] - 1 - k < 0 ? 0 : j[a] - 1 - k;
+            hi[a] = j[a] + k > nc[a] - 1 ? nc[a] - 1 : j[a] + k;
+        }
+        for (int a = 0; a < D; a++) c[a] = lo[a];
+        while (!hit) {
+            int64_t ci = 0;
+            for (int a = 0; a < D; a++) ci = ci * nc[a] + c[a];
+            if (cells[ci]) hit = 1;
+            int a = D - 1;
+            while (a >= 0 && c[a] == hi[a]) {
+                c[a] = lo[a];
+                a--;
+            }
+            if (a < 0) break;
+            c[a]++;
+        }
+        node_mask[i] = (uint8_t)hit;
+        count += hit;
+    }
+    free(cells);
+    return count;
+}
+
+int orc_solve_masked(const orc_dyn* dyn, const orc_grid* g, const double* l,
+                     const double* V0, const double* dlo, const double* dhi,
+                     const double* dfield, const uint8_t* mask, double tol,
+                     double cfl, int order, int64_t max_iter, double* V_out,
+                     int64_t* iterations, double* residual)
+{
+    if (!grid_valid(g) || orc_state_dim(dyn->kind) != g->ndim || !mask) return ORC_EINVAL;
+    if (!(tol > 0.0) || !(cfl > 0.0 && cfl <= 1.0) || max_iter < 1) return ORC_EINVAL;
+    if (order != 1 && order != 2) return ORC_EINVAL;
+    int64_t N = grid_size(g);
+    double alpha[4];
+    orc_lf_alpha_field(dyn, g, dlo, dhi, dfield, alpha);
+    double dt = orc_dt(g, alpha, cfl);
+    double* V = (double*)malloc((size_t)N * sizeof(double));
+    double* Vhat = (double*)malloc((size_t)N * sizeof(double));
+    double* Vn = (double*)malloc((size_t)N * sizeof(double));
+    double* L = (double*)malloc((size_t)N * sizeof(double));
+    for (int64_t i = 0; i < N; i++) {
+        double v0 = V0 ? V0[i] : l[i];
+        V[i] = (l[i] < v0) ? l[i] : v0;
+    }
+    int status = ORC_NOT_CONVERGED;
+    int64_t k;
+    double r = 0.0;
+    for (k = 0; k < max_iter; k++) {
+        /* the RK2 step of orc_iterate at the masked nodes; every other node
+         * keeps its value in both stages (boundary data for the stencils) */
+        orc_spatial_op_field(dyn, g, dlo, dhi, dfield, alpha, order, V, L);
+        for (int64_t i = 0; i < N; i++) Vhat[i] = mask[i] ? V[i] + dt * L[i] : V[i];
+        orc_spatial_op_field(dyn, g, dlo, dhi, dfield, alpha, order, Vhat, L);
+        r = 0.0;
+        for (int64_t i = 0; i < N; i++) {
+            if (!mask[i]) {
+                Vn[i] = V[i];
+                continue;
+            }
+            double Vtil = Vhat[i] + dt * L[i];
+            double avg = 0.5 * (V[i] + Vtil);
+            Vn[i] = (l[i] < avg) ? l[i] : avg;
+            double diff = fabs(Vn[i] - V[i]);
+            if (!(diff <= r)) r = diff;
+        }
+        double* t = V;
+        V = Vn;
+        Vn = t;
+        if (r < tol) {
+            status = ORC_OK;
+            k++;
+            break;
+        }
+    }
+    memcpy(V_out, V, (size_t)N * sizeof(double));
+    *iterations = k;
+    *residual = r;
+    free(V);
+    free(Vhat);
+    free(Vn);
+    free(L);
+    return status;
+}

@@ -226,6 +226,24 @@ int orc_query_decomposed(int nsub, const orc_dyn* dyns, const orc_grid* grids,
                          int32_t* active, double* sub_value, double* grad,
                          double* u_star, double* u_out);
 
+/* Localized update (Sec. VI names localized warm starting as a further
+ * speed-up).  Band of a warm start: node i is in it iff some cell straddling
+ * the zero level set of V (orc_refine_mask) lies within k cells of it: for
+ * every axis, the cell's index range [c_a, c_a + 1] is at most k nodes from
+ * i_a.  Writes node_mask (N bytes) and returns its number of ones. */
+int64_t orc_band_mask(const orc_grid* g, const double* V, int k, uint8_t* node_mask);
+
+/* orc_solve_field restricted to the nodes with mask[i] != 0: both RK stages
+ * and the projection update those nodes only; every other node keeps its
+ * initial value min(l, V0) throughout and serves as boundary data; the
+ * residual runs over the masked nodes (0 if there are none, so the first
+ * step stops).  LF bounds and dt over the whole grid as in orc_solve. */
+int orc_solve_masked(const orc_dyn* dyn, const orc_grid* g, const double* l,
+                     const double* V0, const double* dlo, const double* dhi,
+                     const double* dfield, const uint8_t* mask, double tol,
+                     double cfl, int order, int64_t max_iter, double* V_out,
+                     int64_t* iterations, double* residual);
+
 #ifdef __cplusplus
 }
 #endif

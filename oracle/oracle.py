@@ -99,6 +99,12 @@ def lib():
                                            C.POINTER(C.c_int32), C.POINTER(dp), C.POINTER(dp),
                                            C.c_int, dp, C.c_double, dp, dp,
                                            C.POINTER(C.c_int32), dp, dp, dp, dp]
+        L.orc_band_mask.restype = C.c_int64
+        L.orc_band_mask.argtypes = [gp, dp, C.c_int, C.POINTER(C.c_uint8)]
+        L.orc_solve_masked.restype = C.c_int
+        L.orc_solve_masked.argtypes = [yp, gp, dp, dp, dp, dp, dp, C.POINTER(C.c_uint8),
+                                       C.c_double, C.c_double, C.c_int, C.c_int64, dp,
+                                       C.POINTER(C.c_int64), dp]
         L.orc_query.restype = C.c_int
         L.orc_query.argtypes = [yp, gp, dp, C.c_int, dp, dp, dp, dp, dp, dp]
         L.orc_solve_field.restype = C.c_int
@@ -352,3 +358,31 @@ def query_decomposed(subs, X, level=0.0, U_perf=None, order=2):
         out["sub_value"][i], out["grad"][i], out["u"][i], out["u_out"][i] = sv, g, u, uo
         out["ok"][i] = st == OK
     return out
+
+
+def band_mask(grid: Grid, V, k: int):
+    """Nodes within k cells of a cell straddling V = 0 (uint8 array, count)."""
+    V = _f64(V)
+    m = np.zeros(V.size, dtype=np.uint8)
+    cnt = lib().orc_band_mask(C.byref(grid), _dp(V), int(k), m.ctypes.data_as(C.POINTER(C.c_uint8)))
+    return m, int(cnt)
+
+
+def solve_masked(dyn, grid, l, dlo, dhi, mask, tol=1e-4, V0=None, cfl=0.8, order=2,
+                 max_iter=100000, dfield=None):
+    """Localized solve: only the nodes with mask != 0 are updated."""
+    l = _f64(l)
+    lo, hi = _dbounds(dlo, dhi)
+    keep, fp = _field(grid, dfield)
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    V = np.zeros_like(l)
+    it = C.c_int64(0)
+    res = C.c_double(0)
+    v0p = None
+    if V0 is not None:
+        V0 = _f64(V0)
+        v0p = _dp(V0)
+    st = lib().orc_solve_masked(C.byref(dyn), C.byref(grid), _dp(l), v0p, _dp(lo), _dp(hi), fp,
+                                m.ctypes.data_as(C.POINTER(C.c_uint8)), float(tol), float(cfl),
+                                int(order), int(max_iter), _dp(V), C.byref(it), C.byref(res))
+    return dict(V=V, status=st, iterations=it.value, residual=res.value)
