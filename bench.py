@@ -26,7 +26,9 @@ interval on every grid level, and the roofline of its stage-2 kernel),
 on the converged 41^4 x-subsystem: latency per call and queries/s), --mode
 quad10d (the 10-D model as the paper writes it: initial safe set, then a
 GP-bound update warm-started from the restricted previous value, coarse to
-fine, and 10-D decomposed queries on the result).
+fine, and 10-D decomposed queries on the result), --mode local (a warm
+update of the 41^4 x-subsystem computed over the whole grid and over the
+band of the previous value only).
 """
 from __future__ import annotations
 
@@ -50,7 +52,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "warm", "copy", "precision", "kernels",
-                             "field", "field_kernels", "query", "quad10d"])
+                             "field", "field_kernels", "query", "quad10d", "local"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk", type=int, default=None, help="RK2 steps per chunk (default: autotuned)")
@@ -538,6 +540,49 @@ def mode_quad10d(args, torch, hjr, W):
 
 
 # ---------------------------------------------------------------------------
+# local mode: localized warm-start update
+# ---------------------------------------------------------------------------
+
+def mode_local(args, torch, hjr, W):
+    """x-subsystem 41^4, FP32, residual band 0.5: converge for the bound
+    0.5, then update to 0.55 warm-started from it, (a) over the whole grid,
+    (b) over the band of k = 2 and k = 4 cells around the previous zero
+    level set only (hjr_solve_local); zero-level disagreement of (b)
+    against (a)."""
+    P5 = W.quad_x4d(41, 0.5, band=W.BAND_4D_UPDATE)
+    P55 = W.quad_x4d(41, 0.55, band=W.BAND_4D_UPDATE)
+    spec = hjr.Spec.of(P55)
+    l = torch.tensor(P5.l, dtype=torch.float32, device="cuda")
+    old, _ = hjr.solve(hjr.Spec.of(P5), l)
+
+    def run(fn):
+        fn()
+        ts = []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            V, st = fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return V.clone(), dict(ms_p50=pct(ts, 50), iterations=st["iterations"], status=st["status"],
+                               cell_updates=st["cell_updates"])
+
+    Vfull, full = run(lambda: hjr.solve(spec, l, V0=old))
+    progress(f"local mode full: {full['ms_p50']:.1f} ms, {full['iterations']} steps")
+    out = {"mode": "local", "workload": "x-subsystem 41^4, FP32, warm update of the bound "
+           "0.5 -> 0.55", "full": full}
+    for k in (2, 4):
+        mask, cnt = hjr.band_mask(spec, old, k)
+        Vb, row = run(lambda: hjr.solve_local(spec, l, mask, V0=old))
+        row.update(band_nodes=cnt, band_fraction=cnt / P55.size,
+                   speedup=full["ms_p50"] / row["ms_p50"],
+                   zero_level_disagreement=float((Vfull >= 0).ne(Vb >= 0).float().mean()))
+        out[f"band_k{k}"] = row
+        progress(f"local mode k={k}: {row['ms_p50']:.1f} ms, {row['iterations']} steps")
+    return out
+
+
+# ---------------------------------------------------------------------------
 # batch mode: 256 seeded subsystem solves, plain vs batched
 # ---------------------------------------------------------------------------
 
@@ -807,7 +852,7 @@ def main():
     fn = {"step": mode_step, "batch": mode_batch, "serve": mode_serve, "warm": mode_warm,
           "copy": mode_copy, "precision": mode_precision, "kernels": mode_kernels,
           "field": mode_field, "field_kernels": mode_field_kernels, "query": mode_query,
-          "quad10d": mode_quad10d}[args.mode]
+          "quad10d": mode_quad10d, "local": mode_local}[args.mode]
     out = fn(args, torch, hjr, W)
     print(json.dumps(out), flush=True)
 

@@ -169,7 +169,8 @@ hjr_status hjr_opts_default(hjr_opts* o);
 const char* hjr_strerror(hjr_status s);
 
 /* Bytes of device workspace hjr_solve / hjr_solve_ex needs for one problem on
- * grid g with options o: the stage-1 array and a per-axis table.  (The
+ * grid g with options o: the stage-1 array, a per-axis table and the per-
+ * tile flags of a localized update.  (The
  * library also keeps small per-engine tables -- problem descriptors, residual
  * words, pinned staging, captured graphs -- which it allocates on first use
  * and reuses across calls.)  EINVAL for an invalid grid or dtype. */
@@ -253,6 +254,27 @@ hjr_status hjr_solve_field(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* gri
                            const void* const* l, const void* const* dfield, const void* V0,
                            double tol, const hjr_opts* o, void* const* V_levels,
                            hjr_stats* stats);
+
+/* Localized warm start (Sec. VI names localized warm starting as a further
+ * speed-up): the band of a previous value V on grid g -- node i is in it iff
+ * a cell straddling V = 0 (the cells of hjr_refine_mask) lies within k cells
+ * of it, i.e. for every axis the cell's index range [c_a, c_a + 1] is at
+ * most k nodes from i_a.  node_mask: DEVICE, N bytes (1 in the band, else
+ * 0); *count (host, nullable): nodes in the band.  k >= 0.  Allocates two N-
+ * byte scratch arrays for the call and synchronises o->stream. */
+hjr_status hjr_band_mask(const hjr_grid* g, const void* V, int32_t k, uint8_t* node_mask,
+                         int64_t* count, const hjr_opts* o);
+
+/* Localized update: hjr_solve_ex (d: constant boxes, or dfield: per-node
+ * boxes as in hjr_solve_field, nullable) in which only the nodes with
+ * node_mask[i] != 0 (DEVICE, N bytes) are updated; every other node keeps
+ * its initial value min(l, V0) throughout and serves as boundary data, and
+ * the residual runs over the masked nodes (an empty mask stops after one
+ * step).  Runs on the flat tiles and skips tiles without a masked node.
+ * stats->cell_updates counts masked nodes x steps.  Synchronises o->stream. */
+hjr_status hjr_solve_local(const hjr_dyn* dyn, const hjr_grid* grid, const void* l, const void* V0,
+                           const hjr_dstb* d, const void* dfield, const uint8_t* node_mask,
+                           double tol, const hjr_opts* o, void* V_out, hjr_stats* stats);
 
 /* One independent subsystem problem of a batch (decomposition, Sec. III-A). */
 typedef struct hjr_problem {

@@ -69,7 +69,8 @@ bool same_box(const hjr_grid& a, const hjr_grid& b)
     return true;
 }
 
-// Scratch of one job: the stage-1 array and the lookup table.
+// Scratch of one job: the stage-1 array, the lookup table and the per-tile
+// flags of a localized update.
 size_t job_scratch_bytes(const hjr_grid* grids, int nlev, int dtype)
 {
     int64_t N = 0, n2 = 0;
@@ -77,7 +78,9 @@ size_t job_scratch_bytes(const hjr_grid* grids, int nlev, int dtype)
         N = std::max<int64_t>(N, grid_size(grids[k]));
         if (grids[k].ndim >= 3) n2 = std::max<int64_t>(n2, grids[k].n[2]);
     }
-    return align256(N * elem_size(dtype)) + align256(std::max<int64_t>(n2, 1) * elem_size(dtype));
+    // (a localized update runs on flat tiles: N / kTile of them)
+    return align256(N * elem_size(dtype)) + align256(std::max<int64_t>(n2, 1) * elem_size(dtype)) +
+           align256(N / kTile + 1);
 }
 
 // Idle engines are kept for reuse, keyed by what fixes their device tables,
@@ -190,7 +193,8 @@ struct Session {
     }
 };
 
-void fill_stats(hjr_stats* st, const Job& j, const ProbState& ps, double ms, const Engine& eng)
+void fill_stats(hjr_stats* st, const Job& j, const ProbState& ps, double ms, const Engine& eng,
+                int64_t updated_nodes = -1)
 {
     if (!st) return;
     std::memset(st, 0, sizeof(*st));
@@ -198,7 +202,8 @@ void fill_stats(hjr_stats* st, const Job& j, const ProbState& ps, double ms, con
     for (int k = 0; k < 4; k++) {
         st->level_iterations[k] = j.level_iters[k];
         tot += j.level_iters[k];
-        if (k < j.nlev) cu += grid_size(j.lev[k].grid) * j.level_iters[k];
+        if (k < j.nlev)
+            cu += (updated_nodes >= 0 ? updated_nodes : grid_size(j.lev[k].grid)) * j.level_iters[k];
     }
     st->cell_updates = cu;
     eng.profile(st->kernel_ms, st->kernel_launches, &st->kernel_cell_updates);
@@ -261,7 +266,8 @@ hjr_status solve_levels_impl(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* g
                              const void* const* l, const void* const* dfield, const void* V0,
                              const hjr_dstb* d, double tol, const hjr_opts* o,
                              void* const* V_levels, uint8_t* const* masks,
-                             int64_t* mask_counts, hjr_stats* stats)
+                             int64_t* mask_counts, hjr_stats* stats,
+                             const uint8_t* umask = nullptr)
 {
     const hjr_opts op = resolve(o);
     if (!opts_valid(op)) return HJR_EINVAL;
@@ -309,10 +315,19 @@ hjr_status solve_levels_impl(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* g
             if (st == HJR_EINVAL) ses.clean = true;  // the engine is idle and intact
             return st;
         }
-        int64_t Nmax = 0;
-        for (int k = 0; k < nlev; k++) Nmax = std::max(Nmax, grid_size(grids[k]));
+        int64_t Nmax = 0, n2 = 1;
+        for (int k = 0; k < nlev; k++) {
+            Nmax = std::max(Nmax, grid_size(grids[k]));
+            if (grids[k].ndim >= 3) n2 = std::max<int64_t>(n2, grids[k].n[2]);
+        }
         j.Vhat = ses.ws;
         j.table = ses.ws + align256(Nmax * elem_size(op.dtype));
+        int64_t updated = -1;
+        if (umask) {
+            j.lev[0].umask = umask;
+            j.lev[0].tmask = (uint8_t*)((char*)j.table + align256(n2 * elem_size(op.dtype)));
+            if ((st = eng.count_mask(umask, grid_size(grids[0]), &updated)) != HJR_OK) return st;
+        }
         if ((st = eng.add(&j)) != HJR_OK) return st;
         if ((st = run_engine(eng)) != HJR_OK) return st;
         ProbState ps;
@@ -323,7 +338,7 @@ hjr_status solve_levels_impl(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* g
             for (int k = 0; k < nlev; k++) mask_counts[k] = (int64_t)mc[k];
         }
         const double ms = ses.elapsed_ms();
-        fill_stats(stats, j, ps, ms, eng);
+        fill_stats(stats, j, ps, ms, eng, updated);
         ses.clean = true;
         return (hjr_status)j.status;
     } catch (const std::bad_alloc&) {
@@ -392,6 +407,47 @@ hjr_status hjr_solve_field(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* gri
         if (!dfield[k]) return HJR_EINVAL;
     return solve_levels_impl(dyn, nlev, grids, l, dfield, V0, nullptr, tol, o, V_levels,
                              nullptr, nullptr, stats);
+}
+
+hjr_status hjr_solve_local(const hjr_dyn* dyn, const hjr_grid* grid, const void* l, const void* V0,
+                           const hjr_dstb* d, const void* dfield, const uint8_t* node_mask,
+                           double tol, const hjr_opts* o, void* V_out, hjr_stats* stats)
+{
+    if (!grid || !l || !V_out || !node_mask) return HJR_EINVAL;
+    const void* ls[1] = {l};
+    void* vs[1] = {V_out};
+    const void* fs[1] = {dfield};
+    return solve_levels_impl(dyn, 1, grid, ls, dfield ? fs : nullptr, V0, d, tol, o, vs, nullptr,
+                             nullptr, stats, node_mask);
+}
+
+hjr_status hjr_band_mask(const hjr_grid* g, const void* V, int32_t k, uint8_t* node_mask,
+                         int64_t* count, const hjr_opts* o)
+{
+    const hjr_opts op = resolve(o);
+    if (!g || !V || !node_mask || k < 0) return HJR_EINVAL;
+    if (op.dtype != HJR_F32 && op.dtype != HJR_F64) return HJR_EINVAL;
+    if (!grid_valid(*g)) return HJR_EINVAL;
+    const int64_t N = grid_size(*g);
+    hipStream_t s = (hipStream_t)op.stream;
+    uint8_t* tmp = nullptr;
+    uint64_t* dcount = nullptr;
+    if (hipMalloc(&tmp, 2 * align256(N) + sizeof(uint64_t)) != hipSuccess) return HJR_ENOMEM;
+    dcount = (uint64_t*)(tmp + 2 * align256(N));
+    hjr_status st = HJR_OK;
+    uint64_t h = 0;
+    if (launch_band(s, op.dtype, *g, V, k, tmp, tmp + align256(N), node_mask) != hipSuccess)
+        st = HJR_EDEVICE;
+    if (st == HJR_OK && count &&
+        (launch_fill_u64(s, dcount, 1, 0) != hipSuccess ||
+         launch_tile_flags(s, node_mask, N, 256, nullptr, dcount) != hipSuccess ||
+         hipMemcpyAsync(&h, dcount, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess))
+        st = HJR_EDEVICE;
+    // the scratch is freed once the stream has used it
+    if (hipStreamSynchronize(s) != hipSuccess) st = HJR_EDEVICE;
+    (void)hipFree(tmp);
+    if (st == HJR_OK && count) *count = (int64_t)h;
+    return st;
 }
 
 hjr_status hjr_solve_ex(const hjr_dyn* dyn, const hjr_grid* grid, const void* l, const void* V0,

@@ -158,6 +158,8 @@ struct ProbDesc {
     void* Vhat;              // stage-1 scratch
     void* table;             // per-axis lookup table (g tan(theta) for QUAD_X4D)
     const void* dfield;      // per-node disturbance boxes (channel, lower/upper, node), or null
+    const uint8_t* umask;    // localized update: nodes to update (others keep their value), or null
+    const uint8_t* tmask;    // with umask: per flat tile, whether it holds a node to update
     int64_t tile_begin;      // first global tile of this problem
     int64_t ntiles;
 };

@@ -266,6 +266,17 @@ hjr_status Engine::check_field(const void* f, int nch, int64_t N, int64_t* bad)
     return HJR_OK;
 }
 
+hjr_status Engine::count_mask(const uint8_t* m, int64_t N, int64_t* count)
+{
+    uint64_t h = 0;
+    HJR_TRY(launch_fill_u64(stream_, d_check_, 1, 0));
+    HJR_TRY(launch_tile_flags(stream_, m, N, 256, nullptr, d_check_));  // count only
+    HJR_TRY(hipMemcpyAsync(&h, d_check_, sizeof(h), hipMemcpyDeviceToHost, stream_));
+    HJR_TRY(hipStreamSynchronize(stream_));
+    *count = (int64_t)h;
+    return HJR_OK;
+}
+
 int Engine::free_slots() const
 {
     int n = 0;
@@ -304,6 +315,8 @@ void Engine::fill_desc(const Job* j, ProbDesc& P) const
     P.Vhat = j->Vhat;
     P.table = j->table;
     P.dfield = L.dfield;
+    P.umask = L.umask;
+    P.tmask = L.tmask;
     const int D = g.ndim;
     for (int a = 0; a < D; a++) {
         P.hih[a] = 0.5 / P.h[a];
@@ -347,10 +360,11 @@ void Engine::fill_desc(const Job* j, ProbDesc& P) const
     // else flat tiles of kTile consecutive nodes
     P.path = kPathFlat;
     P.ntiles = (P.N + kTile - 1) / kTile;
-    // (per-node disturbance boxes and QUAD_X4DV have plane families for ENO2 only)
+    // (per-node disturbance boxes and QUAD_X4DV have plane families for ENO2
+    // only; localized updates run on flat tiles)
     const bool plane_kind =
         (P.kind == HJR_QUAD_Z2D || P.kind == HJR_QUAD_X4D || P.kind == HJR_QUAD_X4DV) &&
-        !(cfg_.flags & HJR_FLAG_FLAT_TILES) &&
+        !(cfg_.flags & HJR_FLAG_FLAT_TILES) && !P.umask &&
         !((P.dfield || P.kind == HJR_QUAD_X4DV) && P.order != 2);
     // plane tiles address with 32-bit byte offsets
     const bool fits32 = (double)P.N * (double)elem_size(cfg_.dtype) < 4294967296.0;
@@ -395,6 +409,11 @@ hjr_status Engine::setup_level(Job* j)
         HJR_TRY(launch_interp(stream_, cfg_.dtype, prev.grid, prev.V, L.grid, L.V, L.l));
     }
     HJR_TRY(launch_level_setup(stream_, cfg_.dtype, P, &d_state_[j->slot]));
+    if (L.umask) {
+        // nodes outside the mask keep V, so stage 2 reads Vhat = V there
+        HJR_TRY(launch_copy(stream_, cfg_.dtype, L.V, j->Vhat, P.N));
+        HJR_TRY(launch_tile_flags(stream_, L.umask, P.N, kTile, L.tmask, nullptr));
+    }
     j->sched = 0;
     j->fresh = true;
     j->level_start_chunk = chunk_;

@@ -41,6 +41,8 @@ struct Level {
     uint8_t* mask = nullptr;  // optional refinement-mask output
     int tile_rows = 0;        // LDS tile height, 0 = default
     const void* dfield = nullptr;  // per-node disturbance boxes, or null (Job::d)
+    const uint8_t* umask = nullptr; // localized update: the nodes to update, or null
+    uint8_t* tmask = nullptr;       // scratch for its per-tile flags (flat tiles)
 };
 
 // One solve job: a chain of 1..4 grid levels of one subsystem.
@@ -104,6 +106,9 @@ public:
     // the engine's dtype) whose box is not a finite ordered pair (sync; the
     // engine must be idle).
     hjr_status check_field(const void* f, int nch, int64_t N, int64_t* bad);
+
+    // Number of set bytes of a node mask of N nodes (sync; engine idle).
+    hjr_status count_mask(const uint8_t* m, int64_t N, int64_t* count);
 
     // Copy the per-slot device state (alpha, dt) of a slot to *out (sync).
     hjr_status read_state(int slot, ProbState* out);

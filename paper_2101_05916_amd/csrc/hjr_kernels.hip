@@ -621,6 +621,130 @@ hipError_t launch_field_check(hipStream_t s, int dtype, const void* f, int nch, 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------
+// localized updates: tile flags, band of a warm start, Vhat = V
+// ------------------------------------------------------------------------
+
+// tmask[t] = 1 iff one of the nodes t*tile .. t*tile + tile - 1 is set in
+// umask (tmask nullable); *count += the number of set nodes (count nullable).
+__global__ __launch_bounds__(kBlock) void k_tile_any(const uint8_t* __restrict__ umask, int64_t N,
+                                                     int tile, uint8_t* tmask,
+                                                     unsigned long long* count)
+{
+    __shared__ unsigned long long cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int64_t ntiles = (N + tile - 1) / tile;
+    unsigned long long mine = 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = min((t + 1) * tile, N);
+        int any = 0;
+        for (int64_t i = t * tile; i < e; i++) {
+            const int on = umask[i] != 0;
+            any |= on;
+            mine += on;
+        }
+        if (tmask) tmask[t] = (uint8_t)any;
+    }
+    if (mine) atomicAdd(&cnt, mine);
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt && count) atomicAdd(count, cnt);
+}
+
+// One pass of the band dilation along axis a: the input has extent
+// n_in[b] on each axis (cells on axes >= a, nodes before), the output
+// n_out (nodes on axes <= a); out[.., i_a, ..] = OR over in[.., c, ..] with
+// c in [i_a - 1 - k, i_a + k] within the input's range.
+struct DilateArgs {
+    int D;
+    int a;
+    int k;
+    int n_in[4];
+    int n_out[4];
+    int64_t total;  // output elements
+};
+
+__global__ __launch_bounds__(kBlock) void k_dilate(DilateArgs A, const uint8_t* __restrict__ in,
+                                                   uint8_t* __restrict__ out)
+{
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < A.total;
+         o += (int64_t)gridDim.x * blockDim.x) {
+        int j[4] = {0, 0, 0, 0};
+        int64_t q = o;
+        for (int b = A.D - 1; b >= 0; b--) {
+            j[b] = (int)(q % A.n_out[b]);
+            q /= A.n_out[b];
+        }
+        const int lo = max(j[A.a] - 1 - A.k, 0), hi = min(j[A.a] + A.k, A.n_in[A.a] - 1);
+        int64_t base = 0, stride = 1, sa = 0;
+        for (int b = A.D - 1; b >= 0; b--) {
+            if (b == A.a)
+                sa = stride;
+            else
+                base += (int64_t)j[b] * stride;
+            stride *= A.n_in[b];
+        }
+        uint8_t v = 0;
+        for (int c = lo; c <= hi; c++) v |= in[base + (int64_t)c * sa];
+        out[o] = v ? 1 : 0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy(const T* __restrict__ src, T* __restrict__ dst, int64_t N)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_tile_flags(hipStream_t s, const uint8_t* umask, int64_t N, int tile,
+                             uint8_t* tmask, uint64_t* count)
+{
+    const int64_t ntiles = (N + tile - 1) / tile;
+    hipLaunchKernelGGL(k_tile_any, dim3(grid_for(ntiles, 1024)), dim3(kBlock), 0, s, umask, N, tile,
+                       tmask, (unsigned long long*)count);
+    return hipGetLastError();
+}
+
+hipError_t launch_band(hipStream_t s, int dtype, const hjr_grid& g, const void* V, int k,
+                       uint8_t* tmp0, uint8_t* tmp1, uint8_t* node_mask)
+{
+    // straddling cells, then one dilation pass per axis (cells -> nodes)
+    hipError_t e = launch_mask(s, dtype, g, V, tmp0, nullptr);
+    if (e != hipSuccess) return e;
+    const int D = g.ndim;
+    DilateArgs A;
+    A.D = D;
+    A.k = k;
+    for (int b = 0; b < 4; b++) A.n_in[b] = A.n_out[b] = b < D ? g.n[b] - 1 : 1;
+    const uint8_t* in = tmp0;
+    for (int a = 0; a < D; a++) {
+        A.a = a;
+        A.n_out[a] = g.n[a];
+        A.total = 1;
+        for (int b = 0; b < D; b++) A.total *= A.n_out[b];
+        uint8_t* out = (a == D - 1) ? node_mask : ((a % 2 == 0) ? tmp1 : tmp0);
+        hipLaunchKernelGGL(k_dilate, dim3(grid_for(A.total, 8192)), dim3(kBlock), 0, s, A, in, out);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        in = out;
+        A.n_in[a] = g.n[a];
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_copy(hipStream_t s, int dtype, const void* src, void* dst, int64_t N)
+{
+    const int g = grid_for(N, 4096);
+    if (dtype == HJR_F32)
+        hipLaunchKernelGGL((k_copy<float>), dim3(g), dim3(kBlock), 0, s, (const float*)src, (float*)dst, N);
+    else
+        hipLaunchKernelGGL((k_copy<double>), dim3(g), dim3(kBlock), 0, s, (const double*)src, (double*)dst, N);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(hipStream_t s, uint64_t* p, int64_t n, uint64_t value)
 {
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 1024)), dim3(kBlock), 0, s, p, n, value);

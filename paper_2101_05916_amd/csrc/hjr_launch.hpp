@@ -35,6 +35,16 @@ hipError_t launch_mask(hipStream_t s, int dtype, const hjr_grid& g, const void* 
 hipError_t launch_field_check(hipStream_t s, int dtype, const void* f, int nch, int64_t N,
                               uint64_t* counter);
 
+// Localized updates: per flat tile of `tile` nodes, whether umask sets one
+// of its nodes (*count += set nodes; count nullable); the band of a warm
+// start (nodes within k cells of a cell straddling V = 0; tmp0 and tmp1 are
+// scratch of N bytes each); a plain copy of N elements.
+hipError_t launch_tile_flags(hipStream_t s, const uint8_t* umask, int64_t N, int tile,
+                             uint8_t* tmask, uint64_t* count);
+hipError_t launch_band(hipStream_t s, int dtype, const hjr_grid& g, const void* V, int k,
+                       uint8_t* tmp0, uint8_t* tmp1, uint8_t* node_mask);
+hipError_t launch_copy(hipStream_t s, int dtype, const void* src, void* dst, int64_t N);
+
 // Fill n 64-bit words with value.
 hipError_t launch_fill_u64(hipStream_t s, uint64_t* p, int64_t n, uint64_t value);
 

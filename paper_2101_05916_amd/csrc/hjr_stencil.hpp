@@ -438,10 +438,15 @@ __device__ uint64_t tile_flat(PDesc& P, PState& S, int64_t tile)
     const int N = (int)P.N;
     const T* __restrict__ in = (const T*)(STAGE == 1 ? P.V : P.Vhat);
     uint64_t rmax = 0;
+    // localized update: tiles without a node to update are skipped, and
+    // only the masked nodes are written (the others keep V, and Vhat = V)
+    const uint8_t* umask = P.umask;
+    if (umask && !P.tmask[tile]) return 0;
     const int base = (int)(tile * kTile) + (int)threadIdx.x;
     for (int k = 0; k < kNodesPerThread; k++) {
         const int idx = base + k * kStageBlock;
         if (idx >= N) break;
+        if (umask && !umask[idx]) continue;
         int j[4] = {0, 0, 0, 0};
         uint32_t q = (uint32_t)idx;
 #pragma unroll

@@ -26,7 +26,8 @@ EXPORTS = (
     "hjr_interp", "hjr_refine_mask", "hjr_solve_levels", "hjr_batch_workspace_bytes",
     "hjr_solve_batch", "hjr_server_create", "hjr_server_submit", "hjr_server_poll",
     "hjr_server_wait", "hjr_server_read_value", "hjr_server_memory", "hjr_server_destroy",
-    "hjr_solve_field", "hjr_safety_query", "hjr_safety_query_decomposed",
+    "hjr_solve_field", "hjr_safety_query", "hjr_safety_query_decomposed", "hjr_band_mask",
+    "hjr_solve_local",
 )
 
 
@@ -155,6 +156,11 @@ def lib() -> C.CDLL:
                                   C.c_void_p, C.c_double, P(Opts), P(C.c_void_p), P(Stats)]
     L.hjr_safety_query.restype = st
     L.hjr_safety_query.argtypes = [P(Dyn), P(Grid), C.c_void_p, P(Query), P(Opts)]
+    L.hjr_band_mask.restype = st
+    L.hjr_band_mask.argtypes = [P(Grid), C.c_void_p, C.c_int32, C.c_void_p, P(C.c_int64), P(Opts)]
+    L.hjr_solve_local.restype = st
+    L.hjr_solve_local.argtypes = [P(Dyn), P(Grid), C.c_void_p, C.c_void_p, P(Dstb), C.c_void_p,
+                                  C.c_void_p, C.c_double, P(Opts), C.c_void_p, P(Stats)]
     L.hjr_safety_query_decomposed.restype = st
     L.hjr_safety_query_decomposed.argtypes = [C.c_int32, P(Subsystem), P(QueryDecomposed), P(Opts)]
     L.hjr_batch_workspace_bytes.restype = st
@@ -367,6 +373,50 @@ def solve(spec: Spec, l, V0=None, V_out=None, *, dtype=None, order=2, cfl=0.8,
     if check:
         _raise(r, what, (OK, NOT_CONVERGED))
     del ws
+    out = st.as_dict()
+    out["return"] = r
+    return V_out, out
+
+
+def band_mask(spec: Spec, V, k: int):
+    """Band of the previous value V (hjr_band_mask): a device uint8 tensor of
+    spec.size nodes and the number of nodes in it."""
+    torch = _torch()
+    _check_tensor(V, spec.size, V.dtype, "V")
+    m = torch.empty(spec.size, dtype=torch.uint8, device=V.device)
+    cnt = C.c_int64(0)
+    o = make_opts(V.dtype)
+    g = make_grid(spec.n, spec.lo, spec.hi)
+    _raise(lib().hjr_band_mask(C.byref(g), _ptr(V), int(k), _ptr(m), C.byref(cnt), C.byref(o)),
+           "hjr_band_mask")
+    return m, cnt.value
+
+
+def solve_local(spec: Spec, l, mask, V0=None, V_out=None, *, dtype=None, order=2, cfl=0.8,
+                max_iter=100000, chunk=None, flags=0, dfield=None):
+    """Localized update (hjr_solve_local): only the nodes set in mask (device
+    uint8, spec.size) are updated.  Returns (V_out, stats dict)."""
+    torch = _torch()
+    dtype = dtype or l.dtype
+    N = spec.size
+    _check_tensor(l, N, dtype, "l")
+    _check_tensor(mask, N, torch.uint8, "mask")
+    if V0 is not None:
+        _check_tensor(V0, N, dtype, "V0")
+    if V_out is None:
+        V_out = torch.empty(N, dtype=dtype, device=l.device)
+    if chunk is None:
+        chunk = tuned(spec.kind, dtype, spec.n).get("chunk", 0)
+    o = make_opts(dtype, order, cfl, max_iter, chunk, flags, band=spec.band)
+    g = make_grid(spec.n, spec.lo, spec.hi)
+    dyn = make_dyn(spec.kind, spec.params)
+    d = make_dstb(spec.dlo, spec.dhi)
+    if dfield is not None:
+        _check_field(dfield, spec.kind, N, dtype, "dfield")
+    st = Stats()
+    r = lib().hjr_solve_local(C.byref(dyn), C.byref(g), _ptr(l), _ptr(V0), d, _ptr(dfield),
+                              _ptr(mask), spec.tol, C.byref(o), _ptr(V_out), C.byref(st))
+    _raise(r, "hjr_solve_local", (OK, NOT_CONVERGED))
     out = st.as_dict()
     out["return"] = r
     return V_out, out

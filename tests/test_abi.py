@@ -247,6 +247,27 @@ def test_decomposed_query_rejects_invalid_without_device():
     assert L.hjr_safety_query_decomposed(0, subs, C.byref(q), C.byref(o)) == hjr.EINVAL
 
 
+def test_local_update_rejects_invalid_without_device():
+    L = hjr.lib()
+    dyn = hjr.make_dyn(hjr.QUAD_Z2D, (0.91, 9.81, 7.0, 16.0))
+    g = hjr.make_grid((11, 11), (0, -4), (3, 4))
+    p = C.c_void_p(0x1000)
+    d = hjr.make_dstb((-0.5,), (0.5,))
+    o = hjr.Opts()
+    L.hjr_opts_default(C.byref(o))
+    assert L.hjr_band_mask(C.byref(g), p, -1, p, None, C.byref(o)) == hjr.EINVAL
+    assert L.hjr_band_mask(C.byref(g), None, 2, p, None, C.byref(o)) == hjr.EINVAL
+    bad = hjr.make_grid((2, 11), (0, -4), (3, 4))
+    assert L.hjr_band_mask(C.byref(bad), p, 2, p, None, C.byref(o)) == hjr.EINVAL
+    # no mask, no output, invalid tol: nothing is launched
+    assert L.hjr_solve_local(C.byref(dyn), C.byref(g), p, None, d, None, None, 1e-4, C.byref(o),
+                             p, None) == hjr.EINVAL
+    assert L.hjr_solve_local(C.byref(dyn), C.byref(g), p, None, d, None, p, 1e-4, C.byref(o),
+                             None, None) == hjr.EINVAL
+    assert L.hjr_solve_local(C.byref(dyn), C.byref(g), p, None, d, None, p, -1.0, C.byref(o),
+                             p, None) == hjr.EINVAL
+
+
 def test_batch_and_server_reject_invalid():
     L = hjr.lib()
     out = C.c_size_t(0)
