@@ -26,6 +26,12 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #ifndef HJR_BLOCKS_PER_CU
 #define HJR_BLOCKS_PER_CU 24         // cap on stage workgroups per CU (6 single-wave groups per SIMD)
 #endif
+#ifndef HJR_BLOCKS_PER_CU_S2_BIG
+#define HJR_BLOCKS_PER_CU_S2_BIG 16  // cap for FP32 stage 2 when a family's values exceed
+#endif                               // HJR_BIG_SET_BYTES (fewer tiles in flight stream better)
+#ifndef HJR_BIG_SET_BYTES
+#define HJR_BIG_SET_BYTES (2ll << 30)
+#endif
 #ifndef HJR_BLOCKS_PER_CU_F64
 #define HJR_BLOCKS_PER_CU_F64 14     // the same for the FP64 kernels (15, which their LDS
                                      // allows, measured 17-20 % slower)

@@ -219,6 +219,15 @@ hjr_status Engine::init(hipStream_t stream, void* arena)
             int g = cfg_.grid > 0 ? cfg_.grid : cus * stage_blocks_per_cu(cfg_.dtype, st + 1, f);
             fam_grid_[st][f] = std::max(8, (g + 7) / 8 * 8);
         }
+    // FP32 stage 2 over a family whose V, V-hat and l exceed HJR_BIG_SET_BYTES
+    // (batches of many large problems, streamed from HBM) runs fewer
+    // workgroups per CU: at the full occupancy more tiles are in flight than
+    // the caches serve well, and it measured up to 14 % slower per launch
+    // there, while it is the faster choice for smaller sets
+    for (int f = 0; f < kNumFam; f++)
+        fam_grid_big_[f] = cfg_.grid > 0 || cfg_.dtype != HJR_F32
+                               ? fam_grid_[1][f]
+                               : std::min(fam_grid_[1][f], cus * HJR_BLOCKS_PER_CU_S2_BIG);
     if (profile_)
         for (int q = 0; q < 2; q++) {
             prof_ev_[q].resize(4 * (size_t)K);
@@ -468,6 +477,7 @@ hjr_status Engine::upload_table()
     for (int f = 0; f < kNumFam; f++) {
         fam_tile_[f] = total;
         fam_pos_[f] = pos;
+        fam_nodes_[f] = 0;
         for (int s = 0; s < cap; s++) {
             if (fam_of[s] != f) continue;
             h[s].tile_begin = total;
@@ -475,6 +485,7 @@ hjr_status Engine::upload_table()
             ord[pos] = s;
             pos++;
             total += h[s].ntiles;
+            fam_nodes_[f] += h[s].N;
         }
     }
     fam_tile_[kNumFam] = total;
@@ -617,8 +628,11 @@ hjr_status Engine::step()
         if (nt <= 0) continue;
         Launch l;
         l.fam = fm;
-        for (int st = 0; st < 2; st++)
-            l.grid[st] = (int)std::min<int64_t>(fam_grid_[st][fm], std::max<int64_t>(8, (nt + 7) / 8 * 8));
+        const int64_t set_bytes = fam_nodes_[fm] * 3 * (cfg_.dtype == HJR_F64 ? 8 : 4);
+        for (int st = 0; st < 2; st++) {
+            const int cap = st == 1 && set_bytes > HJR_BIG_SET_BYTES ? fam_grid_big_[fm] : fam_grid_[st][fm];
+            l.grid[st] = (int)std::min<int64_t>(cap, std::max<int64_t>(8, (nt + 7) / 8 * 8));
+        }
         launches_.push_back(l);
     }
     if (use_graph_) {

@@ -168,6 +168,7 @@ private:
     hipEvent_t fork_ev_ = nullptr;
     hipEvent_t join_ev_[kNumFam] = {};
     int fam_grid_[2][kNumFam] = {};  // workgroup cap per stage and family (occupancy x CUs)
+    int fam_grid_big_[kNumFam] = {};  // stage 2's cap when the family's values exceed HJR_BIG_SET_BYTES
     bool own_arena_ = false;
     void* arena_ = nullptr;
     // device tables: problem descriptors, then the family order list (first
@@ -195,6 +196,7 @@ private:
     bool use_graph_ = false;
     std::vector<Launch> launches_;  // stage launches of the current chunk
     int64_t fam_tile_[kNumFam + 1] = {};
+    int64_t fam_nodes_[kNumFam] = {};  // nodes of the problems in the table, per family
     int32_t fam_pos_[kNumFam + 1] = {};
     // bookkeeping
     std::vector<Job*> slots_;

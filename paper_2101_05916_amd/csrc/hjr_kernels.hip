@@ -75,18 +75,16 @@ __device__ __forceinline__ int find_pos(const HJR_CONST int64_t* tb, int lo, int
 
 // Whether problem p still iterates at this step: within its step limit for
 // the chunk, and the previous step's residual (the max of its kResSubs
-// words) not yet below tol.  The wave's lanes load one word each and take
-// the max with a butterfly; readfirstlane makes the decision uniform.
+// words) not yet below tol.  The max is below tol exactly when every word
+// is (the words are bit patterns of non-negative doubles or NaN, whose
+// unsigned order is their order as doubles), so each lane of the wave tests
+// one word and a wave vote decides: one coalesced load, no reduction.
 __device__ __forceinline__ bool prob_active(const ChunkArgs& A, int p)
 {
     static_assert(kResSubs == 64 && kStageBlock == 64, "one residual word per lane of the wave");
     if (A.slot >= ((const HJR_CONST ProbCtl*)A.ctl)[p].limit) return false;
-    uint64_t r = A.res[res_index(p, A.slot, (int)(threadIdx.x & 63), A.K)];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) r = umax64(r, __shfl_xor(r, off, 64));
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)r);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(r >> 32));
-    return !(bitsd(((uint64_t)hi << 32) | lo) < ((PDesc*)A.probs)[p].tol);
+    const uint64_t r = A.res[res_index(p, A.slot, (int)(threadIdx.x & 63), A.K)];
+    return __any(!(bitsd(r) < ((PDesc*)A.probs)[p].tol));
 }
 
 // Fold a workgroup's max |V' - V| into problem p's residual of this step.
