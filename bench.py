@@ -809,12 +809,14 @@ def mode_copy(args, torch, hjr, W):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_stage_decomposed_quad10d.json")
-KERNEL_SOURCES = ["csrc/hjr_stencil.hpp", "csrc/hjr_kernels.hip", "csrc/hjr_device.hpp", "tuned.json"]
+KERNEL_SOURCES = ["csrc/hjr_stencil.hpp", "csrc/hjr_kernels.hip", "csrc/hjr_device.hpp",
+                  "csrc/hjr_engine.cpp", "tuned.json"]
 
 
 def kernel_hash():
     """Hash of what defines the stage kernels' memory traffic: their sources
-    (tile code, launch caps) and the tuned tile heights."""
+    (tile code, launch caps), the engine that sizes their launches and the
+    tuned tile heights."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:

@@ -28,7 +28,7 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #endif
 #ifndef HJR_BLOCKS_PER_CU_S2_BIG
 #define HJR_BLOCKS_PER_CU_S2_BIG 16  // cap for FP32 stage 2 when a family's values exceed
-#endif                               // HJR_BIG_SET_BYTES (fewer tiles in flight stream better)
+#endif                               // HJR_BIG_SET_BYTES or other families run beside it
 #ifndef HJR_BIG_SET_BYTES
 #define HJR_BIG_SET_BYTES (2ll << 30)
 #endif

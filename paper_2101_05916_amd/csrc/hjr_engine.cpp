@@ -219,11 +219,14 @@ hjr_status Engine::init(hipStream_t stream, void* arena)
             int g = cfg_.grid > 0 ? cfg_.grid : cus * stage_blocks_per_cu(cfg_.dtype, st + 1, f);
             fam_grid_[st][f] = std::max(8, (g + 7) / 8 * 8);
         }
-    // FP32 stage 2 over a family whose V, V-hat and l exceed HJR_BIG_SET_BYTES
-    // (batches of many large problems, streamed from HBM) runs fewer
-    // workgroups per CU: at the full occupancy more tiles are in flight than
-    // the caches serve well, and it measured up to 14 % slower per launch
-    // there, while it is the faster choice for smaller sets
+    // FP32 stage 2 runs fewer workgroups per CU over a family whose V, V-hat
+    // and l exceed HJR_BIG_SET_BYTES (batches of many large problems,
+    // streamed from HBM: at full occupancy more tiles are in flight than the
+    // caches serve well, up to 14 % slower per launch) and while other
+    // families run beside it on the side streams (it would otherwise hold
+    // every workgroup slot: served mixes of 2-D and 4-D instances measured
+    // 10 % more updates/s with the cap); a lone family of a smaller set runs
+    // at full occupancy, the faster choice there
     for (int f = 0; f < kNumFam; f++)
         fam_grid_big_[f] = cfg_.grid > 0 || cfg_.dtype != HJR_F32
                                ? fam_grid_[1][f]
@@ -623,14 +626,17 @@ hjr_status Engine::step()
     // one launch per family present, with no more workgroups than it has
     // tiles (a multiple of 8, so that every XCD gets its share)
     launches_.clear();
+    int nfam = 0;  // families launched side by side in this chunk
+    for (int fm = 0; fm < kNumFam; fm++) nfam += fam_tile_[fm + 1] > fam_tile_[fm];
     for (int fm = 0; fm < kNumFam; fm++) {
         const int64_t nt = fam_tile_[fm + 1] - fam_tile_[fm];
         if (nt <= 0) continue;
         Launch l;
         l.fam = fm;
         const int64_t set_bytes = fam_nodes_[fm] * 3 * (cfg_.dtype == HJR_F64 ? 8 : 4);
+        const bool capped = set_bytes > HJR_BIG_SET_BYTES || nfam > 1;
         for (int st = 0; st < 2; st++) {
-            const int cap = st == 1 && set_bytes > HJR_BIG_SET_BYTES ? fam_grid_big_[fm] : fam_grid_[st][fm];
+            const int cap = st == 1 && capped ? fam_grid_big_[fm] : fam_grid_[st][fm];
             l.grid[st] = (int)std::min<int64_t>(cap, std::max<int64_t>(8, (nt + 7) / 8 * 8));
         }
         launches_.push_back(l);
