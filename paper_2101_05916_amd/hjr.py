@@ -476,6 +476,10 @@ def make_problem(spec: Spec, l, V_out, V0=None, levels=None, tile_rows=None,
     p.dyn = make_dyn(spec.kind, spec.params)
     if levels is None:
         levels = [(spec.n, l, V_out)]
+    dts = {t.dtype for _, lk, Vk in levels for t in (lk, Vk)}
+    if len(dts) != 1:
+        raise ValueError(f"make_problem: the level arrays mix dtypes {sorted(map(str, dts))}")
+    p._dtype = dts.pop()  # solve_batch runs the kernels of this precision
     p.nlev = len(levels)
     for k, (n, lk, Vk) in enumerate(levels):
         p.grids[k] = make_grid(n, spec.lo, spec.hi)
@@ -502,10 +506,18 @@ def make_problem(spec: Spec, l, V_out, V0=None, levels=None, tile_rows=None,
 
 def solve_batch(problems, *, dtype=None, order=2, cfl=0.8, max_iter=100000, chunk=None,
                 flags=0, device=None):
-    """problems: list of Problem structs (make_problem).  chunk None takes the
-    autotuned chunk of the largest grid in the batch.  Returns (return
-    status, list of stats dicts)."""
+    """problems: list of Problem structs (make_problem).  dtype None takes the
+    precision of the problems' arrays (all alike); a dtype that differs from
+    it is an error.  chunk None takes the autotuned chunk of the largest grid
+    in the batch.  Returns (return status, list of stats dicts)."""
     torch = _torch()
+    have = {getattr(p, "_dtype", None) for p in problems} - {None}
+    if len(have) > 1:
+        raise ValueError(f"solve_batch: the problems mix dtypes {sorted(map(str, have))}")
+    if dtype is None:
+        dtype = have.pop() if have else torch.float32
+    elif have and dtype not in have:
+        raise ValueError(f"solve_batch: dtype {dtype} differs from the problems' arrays ({have.pop()})")
     n = len(problems)
     if chunk is None:
         big = max(problems, key=lambda p: max(int(np.prod([p.grids[k].n[i] for i in range(p.grids[k].ndim)]))

@@ -280,3 +280,27 @@ def test_batch_and_server_reject_invalid():
     assert L.hjr_server_submit(None, None, None) == hjr.EINVAL
     assert L.hjr_server_poll(None, 1, None) == hjr.EINVAL
     assert L.hjr_server_destroy(None) == hjr.EINVAL
+
+
+def test_batch_binding_takes_the_arrays_precision():
+    """solve_batch runs the kernels of the problems' precision: a batch that
+    mixes FP32 and FP64 arrays, or a dtype that differs from theirs, is
+    refused before anything is launched."""
+    torch = pytest.importorskip("torch")
+    from paper_2101_05916_amd import workloads as W
+    P = W.quad_z2d(11, 0.5)
+    spec = hjr.Spec.of(P)
+
+    def prob(dt):
+        l = torch.tensor(P.l, dtype=dt)
+        return hjr.make_problem(spec, l, torch.empty_like(l), tile_rows=[1])
+
+    p32, p64 = prob(torch.float32), prob(torch.float64)
+    assert p32._dtype == torch.float32 and p64._dtype == torch.float64
+    with pytest.raises(ValueError, match="mix dtypes"):
+        hjr.solve_batch([p32, p64], chunk=4)
+    with pytest.raises(ValueError, match="differs"):
+        hjr.solve_batch([p64], dtype=torch.float32, chunk=4)
+    l = torch.tensor(P.l, dtype=torch.float32)
+    with pytest.raises(ValueError, match="mix dtypes"):
+        hjr.make_problem(spec, l, torch.empty(P.size, dtype=torch.float64), tile_rows=[1])
