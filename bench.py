@@ -125,8 +125,9 @@ def cpu_baseline(seconds, W):
 def profile_dominant(torch, hjr, W, chunk, steps=512):
     """Device time per launch of the dominant kernel, measured with HIP
     events on the engine's stream (HJR_FLAG_PROFILE times the stage launches
-    of one chunk in eight): the step's two 4-D subsystems on their fine
-    41^4 grid, batched as in the step, for a fixed number of RK2 steps."""
+    of one chunk in eight, the events stamped at each kernel's own start and
+    end): the step's two 4-D subsystems on their fine 41^4 grid, batched as
+    in the step, for a fixed number of RK2 steps."""
     Ps = [W.quad_x4d(41, 0.5, "x"), W.quad_x4d(41, 0.5, "y")]
     ls = [torch.tensor(P.l, dtype=torch.float32, device="cuda") for P in Ps]
     Vs = [torch.empty_like(l) for l in ls]

@@ -136,8 +136,9 @@ typedef struct hjr_opts {
 #define HJR_FLAG_NO_GRAPH 1     /* launch chunks kernel by kernel, no hipGraph */
 #define HJR_FLAG_NO_PIPELINE 2  /* wait for each chunk before enqueuing the next */
 #define HJR_FLAG_PROFILE 4      /* time the RK-stage launches of one chunk in
-                                   eight with HIP events (implies
-                                   HJR_FLAG_NO_GRAPH) */
+                                   eight with HIP events stamped at each
+                                   stage's first kernel start and last kernel
+                                   end (implies HJR_FLAG_NO_GRAPH) */
 #define HJR_FLAG_FLAT_TILES 8   /* use the shape-agnostic flat tiles only (the
                                    LDS plane tiles are the default where the
                                    last axis has <= 204 nodes) */

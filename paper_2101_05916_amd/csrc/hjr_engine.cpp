@@ -523,12 +523,16 @@ ChunkArgs Engine::args(int par, int slot) const
 // the second and later families go to side streams that fork from and join
 // back into the engine stream, so the captured graph runs them as parallel
 // branches; the first family stays on the engine stream.
-hjr_status Engine::enqueue_stage(int stage, const ChunkArgs& a, bool fork)
+hjr_status Engine::enqueue_stage(int stage, const ChunkArgs& a, bool fork, hipEvent_t e0, hipEvent_t e1)
 {
     const int n = (int)launches_.size();
     if (!fork || n < 2) {
-        for (const Launch& l : launches_)
-            HJR_TRY(launch_stage(stream_, cfg_.dtype, stage, l.fam, a, l.grid[stage - 1]));
+        // e0 / e1 (timed chunks) stamp the first kernel's start and the last one's end
+        for (int i = 0; i < n; i++) {
+            const Launch& l = launches_[i];
+            HJR_TRY(launch_stage(stream_, cfg_.dtype, stage, l.fam, a, l.grid[stage - 1],
+                                 i == 0 ? e0 : nullptr, i == n - 1 ? e1 : nullptr));
+        }
         return HJR_OK;
     }
     HJR_TRY(hipEventRecord(fork_ev_, stream_));
@@ -549,10 +553,10 @@ hjr_status Engine::enqueue_chunk_body(int par, bool timed, bool fork)
     for (int s = 0; s < cfg_.K; s++) {
         const ChunkArgs a = args(par, s);
         for (int stage = 1; stage <= 2; stage++) {
-            if (timed) HJR_TRY(hipEventRecord(prof_ev_[par][4 * s + 2 * (stage - 1)], stream_));
-            hjr_status st = enqueue_stage(stage, a, fork);
+            hipEvent_t e0 = timed ? prof_ev_[par][4 * s + 2 * (stage - 1)] : nullptr;
+            hipEvent_t e1 = timed ? prof_ev_[par][4 * s + 2 * (stage - 1) + 1] : nullptr;
+            hjr_status st = enqueue_stage(stage, a, fork && !timed, e0, e1);
             if (st != HJR_OK) return st;
-            if (timed) HJR_TRY(hipEventRecord(prof_ev_[par][4 * s + 2 * (stage - 1) + 1], stream_));
         }
     }
     HJR_TRY(launch_epilogue(stream_, args(par, 0)));

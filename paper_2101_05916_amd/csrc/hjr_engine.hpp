@@ -142,7 +142,8 @@ private:
     hjr_status setup_level(Job* j);
     hjr_status upload_table();
     hjr_status enqueue_chunk_body(int par, bool timed, bool fork);
-    hjr_status enqueue_stage(int stage, const ChunkArgs& a, bool fork);
+    hjr_status enqueue_stage(int stage, const ChunkArgs& a, bool fork, hipEvent_t e0 = nullptr,
+                             hipEvent_t e1 = nullptr);
     hjr_status build_graph(int par, hipGraphExec_t* out);
     hjr_status process(Flight& f);
     void finish_level(Job* j, int status, int64_t iters, double residual);

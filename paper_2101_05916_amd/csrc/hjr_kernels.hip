@@ -20,6 +20,7 @@
 // first reads the residual of iteration s-1 and skips the problem if it is
 // already below tol, so a chunk of K iterations can be enqueued blind and
 // still stops at exactly the right step.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -492,40 +493,54 @@ hipError_t launch_epilogue(hipStream_t s, const ChunkArgs& a)
     return hipGetLastError();
 }
 
+// One stage kernel.  With events (the timed chunks of HJR_FLAG_PROFILE) the
+// runtime stamps them at the kernel's own start and end, so the measured
+// time holds no gap between launches.
+template <typename T, int STAGE, int FAM>
+static void launch_one(hipStream_t s, dim3 g, dim3 b, const ChunkArgs& a, hipEvent_t e0, hipEvent_t e1)
+{
+    if (e0 || e1)
+        hipExtLaunchKernelGGL((k_stage<T, STAGE, FAM>), g, b, 0, s, e0, e1, 0, a);
+    else
+        hipLaunchKernelGGL((k_stage<T, STAGE, FAM>), g, b, 0, s, a);
+}
+
 template <typename T, int STAGE>
-static hipError_t launch_stage_t(hipStream_t s, int fam, const ChunkArgs& a, int grid)
+static hipError_t launch_stage_t(hipStream_t s, int fam, const ChunkArgs& a, int grid, hipEvent_t e0,
+                                 hipEvent_t e1)
 {
     const dim3 g(grid), b(kStageBlock);
     switch (fam) {
-    case kFamFlat: hipLaunchKernelGGL((k_stage<T, STAGE, kFamFlat>), g, b, 0, s, a); break;
-    case kFamZ2dS2: hipLaunchKernelGGL((k_stage<T, STAGE, kFamZ2dS2>), g, b, 0, s, a); break;
-    case kFamZ2dL2: hipLaunchKernelGGL((k_stage<T, STAGE, kFamZ2dL2>), g, b, 0, s, a); break;
-    case kFamX4dS2: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dS2>), g, b, 0, s, a); break;
-    case kFamX4dL2: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dL2>), g, b, 0, s, a); break;
-    case kFamZ2dS1: hipLaunchKernelGGL((k_stage<T, STAGE, kFamZ2dS1>), g, b, 0, s, a); break;
-    case kFamZ2dL1: hipLaunchKernelGGL((k_stage<T, STAGE, kFamZ2dL1>), g, b, 0, s, a); break;
-    case kFamX4dS1: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dS1>), g, b, 0, s, a); break;
-    case kFamX4dL1: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dL1>), g, b, 0, s, a); break;
-    case kFamZ2dS2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamZ2dS2F>), g, b, 0, s, a); break;
-    case kFamZ2dL2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamZ2dL2F>), g, b, 0, s, a); break;
-    case kFamX4dS2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dS2F>), g, b, 0, s, a); break;
-    case kFamX4dL2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamX4dL2F>), g, b, 0, s, a); break;
-    case kFamXvS2: hipLaunchKernelGGL((k_stage<T, STAGE, kFamXvS2>), g, b, 0, s, a); break;
-    case kFamXvL2: hipLaunchKernelGGL((k_stage<T, STAGE, kFamXvL2>), g, b, 0, s, a); break;
-    case kFamXvS2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamXvS2F>), g, b, 0, s, a); break;
-    case kFamXvL2F: hipLaunchKernelGGL((k_stage<T, STAGE, kFamXvL2F>), g, b, 0, s, a); break;
+    case kFamFlat: launch_one<T, STAGE, kFamFlat>(s, g, b, a, e0, e1); break;
+    case kFamZ2dS2: launch_one<T, STAGE, kFamZ2dS2>(s, g, b, a, e0, e1); break;
+    case kFamZ2dL2: launch_one<T, STAGE, kFamZ2dL2>(s, g, b, a, e0, e1); break;
+    case kFamX4dS2: launch_one<T, STAGE, kFamX4dS2>(s, g, b, a, e0, e1); break;
+    case kFamX4dL2: launch_one<T, STAGE, kFamX4dL2>(s, g, b, a, e0, e1); break;
+    case kFamZ2dS1: launch_one<T, STAGE, kFamZ2dS1>(s, g, b, a, e0, e1); break;
+    case kFamZ2dL1: launch_one<T, STAGE, kFamZ2dL1>(s, g, b, a, e0, e1); break;
+    case kFamX4dS1: launch_one<T, STAGE, kFamX4dS1>(s, g, b, a, e0, e1); break;
+    case kFamX4dL1: launch_one<T, STAGE, kFamX4dL1>(s, g, b, a, e0, e1); break;
+    case kFamZ2dS2F: launch_one<T, STAGE, kFamZ2dS2F>(s, g, b, a, e0, e1); break;
+    case kFamZ2dL2F: launch_one<T, STAGE, kFamZ2dL2F>(s, g, b, a, e0, e1); break;
+    case kFamX4dS2F: launch_one<T, STAGE, kFamX4dS2F>(s, g, b, a, e0, e1); break;
+    case kFamX4dL2F: launch_one<T, STAGE, kFamX4dL2F>(s, g, b, a, e0, e1); break;
+    case kFamXvS2: launch_one<T, STAGE, kFamXvS2>(s, g, b, a, e0, e1); break;
+    case kFamXvL2: launch_one<T, STAGE, kFamXvL2>(s, g, b, a, e0, e1); break;
+    case kFamXvS2F: launch_one<T, STAGE, kFamXvS2F>(s, g, b, a, e0, e1); break;
+    case kFamXvL2F: launch_one<T, STAGE, kFamXvL2F>(s, g, b, a, e0, e1); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_stage(hipStream_t s, int dtype, int stage, int fam, const ChunkArgs& a, int grid)
+hipError_t launch_stage(hipStream_t s, int dtype, int stage, int fam, const ChunkArgs& a, int grid,
+                        hipEvent_t e0, hipEvent_t e1)
 {
     if (dtype == HJR_F32)
-        return stage == 1 ? launch_stage_t<float, 1>(s, fam, a, grid)
-                          : launch_stage_t<float, 2>(s, fam, a, grid);
-    return stage == 1 ? launch_stage_t<double, 1>(s, fam, a, grid)
-                      : launch_stage_t<double, 2>(s, fam, a, grid);
+        return stage == 1 ? launch_stage_t<float, 1>(s, fam, a, grid, e0, e1)
+                          : launch_stage_t<float, 2>(s, fam, a, grid, e0, e1);
+    return stage == 1 ? launch_stage_t<double, 1>(s, fam, a, grid, e0, e1)
+                      : launch_stage_t<double, 2>(s, fam, a, grid, e0, e1);
 }
 
 hipError_t launch_level_setup(hipStream_t s, int dtype, const ProbDesc& P, ProbState* st)

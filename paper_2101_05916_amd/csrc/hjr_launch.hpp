@@ -11,7 +11,9 @@ namespace hjr {
 // Iteration kernels (one chunk = prologue, K x (stage 1, stage 2), epilogue).
 hipError_t launch_prologue(hipStream_t s, const ChunkArgs& a);
 // One RK stage over the tiles of family fam (see Family).
-hipError_t launch_stage(hipStream_t s, int dtype, int stage, int fam, const ChunkArgs& a, int grid);
+// e0 / e1, when given, are stamped at the kernel's start / end.
+hipError_t launch_stage(hipStream_t s, int dtype, int stage, int fam, const ChunkArgs& a, int grid,
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_epilogue(hipStream_t s, const ChunkArgs& a);
 
 // Per-level set-up of one problem: Lax-Friedrichs bounds, time step and
