@@ -79,6 +79,27 @@ def test_batch_stops_each_problem_at_its_own_step():
         assert np.max(np.abs(V.cpu().numpy() - ref["V"])) <= 5e-5
 
 
+def test_batch_takes_the_precision_of_its_arrays():
+    """FP64 problems solved without a dtype run the FP64 kernels: the same
+    step counts and values as with dtype=float64 (once the binding ran the
+    FP32 kernels over such buffers), and the oracle's step counts."""
+    hjr = hjr_()
+    Ps = [W.quad_z2d(51, 0.5), W.quad_x4d(9, 0.5)]
+    out = []
+    for dtype in (None, torch.float64):
+        ls = [dev(P.l, torch.float64) for P in Ps]
+        Vs = [torch.empty_like(l) for l in ls]
+        probs = [hjr.make_problem(hjr.Spec.of(P), l, V) for P, l, V in zip(Ps, ls, Vs)]
+        r, stats = hjr.solve_batch(probs, dtype=dtype, max_iter=20000)
+        torch.cuda.synchronize()
+        assert r == hjr.OK
+        out.append((Vs, stats))
+    (Va, sa), (Vb, sb) = out
+    for P, a, b, x, y in zip(Ps, Va, Vb, sa, sb):
+        assert x["iterations"] == y["iterations"] == oracle_solve(P)["iterations"], P.name
+        assert torch.equal(a, b), P.name
+
+
 def test_batch_not_converged_status():
     hjr = hjr_()
     Ps = [W.quad_z2d(51, 0.5), W.quad_z2d(101, 0.5)]
