@@ -26,6 +26,9 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #ifndef HJR_BLOCKS_PER_CU
 #define HJR_BLOCKS_PER_CU 24         // cap on stage workgroups per CU (6 single-wave groups per SIMD)
 #endif
+#ifndef HJR_BLOCKS_PER_CU_S2
+#define HJR_BLOCKS_PER_CU_S2 20      // cap for the FP32 stage-2 kernels (0: HJR_BLOCKS_PER_CU); the
+#endif                               // 24 their registers allow measured up to 8 % slower per launch
 #ifndef HJR_BLOCKS_PER_CU_S2_BIG
 #define HJR_BLOCKS_PER_CU_S2_BIG 16  // cap for FP32 stage 2 when a family's values exceed
 #endif                               // HJR_BIG_SET_BYTES or other families run beside it

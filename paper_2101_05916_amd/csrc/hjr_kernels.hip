@@ -88,22 +88,25 @@ __device__ __forceinline__ bool prob_active(const ChunkArgs& A, int p)
     return __any(!(bitsd(r) < ((PDesc*)A.probs)[p].tol));
 }
 
+// The residual word of problem p at this step that this workgroup folds into.
+__device__ __forceinline__ unsigned long long* residual_word(const ChunkArgs& A, int p)
+{
+    return (unsigned long long*)&A.res[res_index(p, A.slot + 1, blockIdx.x % kResSubs, A.K)];
+}
+
 // Fold a workgroup's max |V' - V| into problem p's residual of this step.
 // The residual is spread over kResSubs words (the reader takes their max),
-// and the atomic is skipped when the word already holds at least this value
-// -- the words only grow, so a stale read can only cause a redundant
-// atomic, never a lost one.  Few workgroups beat the running max, so the
-// device-scope atomics on any one word stay few.
+// and the atomic is skipped when the word already held at least this value
+// when read (`seen`, read as the workgroup began the problem's tiles, so
+// that the read's latency overlaps them) -- the words only grow, so a stale
+// read can only cause a redundant atomic, never a lost one.  Few workgroups
+// beat the running max, so the device-scope atomics on any one word stay few.
 template <int NB>
-__device__ __forceinline__ void flush_residual(const ChunkArgs& A, int p, uint64_t rmax, uint64_t* red)
+__device__ __forceinline__ void flush_residual(const ChunkArgs& A, int p, uint64_t rmax, uint64_t* red,
+                                               uint64_t seen)
 {
     const uint64_t r = block_max_u64<NB>(rmax, red);
-    if (threadIdx.x == 0) {
-        unsigned long long* w =
-            (unsigned long long*)&A.res[res_index(p, A.slot + 1, blockIdx.x % kResSubs, A.K)];
-        const unsigned long long seen = __atomic_load_n(w, __ATOMIC_RELAXED);
-        if (r > seen) atomicMax(w, (unsigned long long)r);
-    }
+    if (threadIdx.x == 0 && r > seen) atomicMax(residual_word(A, p), (unsigned long long)r);
 }
 
 // Occupancy hint per stage (0 = none): asks the compiler to fit the stage
@@ -150,21 +153,22 @@ __global__ __launch_bounds__(kStageBlock) HJR_STAGE_ATTR void k_stage(ChunkArgs 
     int cur = -1;
     int64_t lo = 0, hi = 0;  // tile range of the current problem
     bool active = false;
-    uint64_t rmax = 0;
+    uint64_t rmax = 0, seen = 0;
     for (int64_t t = beg + local; t < end; t += G8) {
         if (t >= hi || t < lo) {
             const int pos = find_pos(tb, pb, pe, t);
-            if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red);
+            if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red, seen);
             cur = ord[pos];
             lo = tb[pos];
             hi = pos + 1 < pe ? tb[pos + 1] : t1;
             rmax = 0;
             active = prob_active(A, cur);
+            if (STAGE == 2 && active) seen = __atomic_load_n(residual_word(A, cur), __ATOMIC_RELAXED);
         }
         if (!active) continue;
         rmax = umax64(rmax, run_tile<T, STAGE, FAM>(probs[cur], states[cur], (uint32_t)(t - lo), lds));
     }
-    if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red);
+    if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red, seen);
 }
 
 // Chunk prologue: one workgroup per problem slot.  Slot 0 of the residual
@@ -802,7 +806,8 @@ int stage_blocks_per_cu(int dtype, int stage, int fam)
     int n = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kStageBlock, 0);
     if (e != hipSuccess || n < 1) n = 2;
-    const int cap = dtype == HJR_F64 ? HJR_BLOCKS_PER_CU_F64 : HJR_BLOCKS_PER_CU;
+    int cap = dtype == HJR_F64 ? HJR_BLOCKS_PER_CU_F64 : HJR_BLOCKS_PER_CU;
+    if (dtype == HJR_F32 && stage == 2 && HJR_BLOCKS_PER_CU_S2 > 0) cap = HJR_BLOCKS_PER_CU_S2;
     if (cap > 0 && cap < n) n = cap;
     return n;
 }
