@@ -65,6 +65,26 @@ def test_batch_bit_identical_to_single(flags):
         assert torch.equal(V, Vs1), P.name
 
 
+def test_large_family_runs_capped_and_matches_single():
+    """A family whose V, V-hat and l exceed 2 GiB runs FP32 stage 2 with
+    fewer workgroups per CU; the kernels stride over tiles, so every
+    problem's result equals its single solve bit for bit."""
+    hjr = hjr_()
+    P = W.quad_x4d(61, 0.5)
+    count = 14  # 14 x 61^4 nodes x 12 B = 2.3 GB
+    assert count * P.size * 12 > 2 << 30
+    l = dev(P.l)
+    Vs = [torch.empty_like(l) for _ in range(count)]
+    probs = [hjr.make_problem(hjr.Spec.of(P), l, V) for V in Vs]
+    r, stats = hjr.solve_batch(probs, max_iter=6, chunk=4)
+    torch.cuda.synchronize()
+    assert r == hjr.NOT_CONVERGED
+    V1, st1 = single(P, max_iter=6, chunk=4)
+    for V, st in zip(Vs, stats):
+        assert st["iterations"] == st1["iterations"] == 6
+        assert torch.equal(V, V1)
+
+
 def test_batch_stops_each_problem_at_its_own_step():
     hjr = hjr_()
     Ps = [W.quad_z2d(51, 0.5), W.quad_z2d(101, 0.5), W.quad_z2d(101, 0.0)]
