@@ -1,34 +1,38 @@
 """Benchmark of the HJ-reachability safe-set solve on one MI355X.
 
-Default workload (one "step"): the initial safe-set computation of the
-near-hover quadcopter decomposed into its x, y (4-D, 41^4) and z (2-D, 101^2)
-subsystems, FP32, disturbance bound 0.5, each subsystem solved coarse-to-fine
-(21^4 -> 41^4, 51^2 -> 101^2) from a cold start, all three in one batched
-device solve.  Every step runs the whole path: level set-up, initialisation,
-both RK stages, the residual reduction and stop test, the level transition
-and the decomposed batch.
+Default workload (one "step", --mode mix): the batched mix of 256 independent
+subsystem safe-set solves -- a seeded draw (numpy default_rng(0)) of 2-D
+vertical-quadcopter problems on 51^2 .. 201^2 and 4-D x-subsystem problems
+on 31^4 .. 61^4 (121 of them, 6.5e8 nodes, 7.8 GB of FP32 V, Vhat and l),
+disturbance bounds uniform in [0.2, 1.0], every one solved from a cold start
+to convergence (tol 1e-4; the 4-D ones over the residual band |V| < 0.5) in
+one batched device solve: captured chunk graphs, autotuned tile heights.
+Every step runs the whole path: level set-up, initialisation, both RK stages,
+the residual reduction and stop test, and the decomposed batch.
 
-Metric: grid cell-updates per second (nodes x RK2 steps, summed over levels
-and subsystems, divided by wall time; the timed steps run the library's
-default path: captured graphs, one chunk in flight).  The JSON line also
-carries p50/p99 of the per-step safe-set latency, the HBM roofline of the
-dominant kernel (RK stage 2 of the 4-D subsystems) from HIP-event timings of
-its launches in a separate profiled pass, and the oracle's rate on the host
-CPU.
+Metric: grid cell-updates per second (nodes x RK2 steps summed over the 256
+problems, divided by the wall time of the timed steps).  The JSON line also
+carries p50/p99 of the batch latency, safe-set updates/s, the HBM roofline of
+the dominant kernel (RK stage 2 of the 4-D family, timed with HIP events on
+the engine's stream in a separate pass over the 121 4-D problems, all live,
+7.8 GB streamed from HBM each stage) and the oracle's rate on every host
+core it may use, on a bounded sample of the same problems.
 
-Other modes (not the headline line): --mode batch (256 seeded subsystem
-solves, plain one-solve-per-call vs batched), --mode serve (Poisson request
-stream through the continuous-batching server), --mode warm (warm start and
-coarse-to-fine vs cold on the 4-D x-subsystem), --mode field (the same
-decomposed solve with state-dependent disturbance bounds, a per-node
-interval on every grid level, and the roofline of its stage-2 kernel),
---mode query (safety queries -- value, gradient, optimal control, filter --
-on the converged 41^4 x-subsystem: latency per call and queries/s), --mode
-quad10d (the 10-D model as the paper writes it: initial safe set, then a
-GP-bound update warm-started from the restricted previous value, coarse to
-fine, and 10-D decomposed queries on the result), --mode local (a warm
-update of the 41^4 x-subsystem computed over the whole grid and over the
-band of the previous value only).
+Other modes (not the headline line): --mode step (the decomposed near-hover
+quadcopter's initial safe set: x, y 21^4 -> 41^4 and z 51^2 -> 101^2 in one
+batched solve), --mode batch (the same 256 solves, plain one-solve-per-call
+vs batched), --mode serve (Poisson request stream through the continuous-
+batching server), --mode warm (warm start and coarse-to-fine vs cold on the
+4-D x-subsystem), --mode field (the decomposed solve with state-dependent
+disturbance bounds, a per-node interval on every grid level, and the roofline
+of its stage-2 kernel), --mode query (safety queries -- value, gradient,
+optimal control, filter -- on the converged 41^4 x-subsystem: latency per
+call and queries/s), --mode quad10d (the 10-D model as the paper writes it:
+initial safe set, then a GP-bound update warm-started from the restricted
+previous value, coarse to fine, and 10-D decomposed queries on the result),
+--mode local (a warm update of the 41^4 x-subsystem computed over the whole
+grid and over the band of the previous value only), --mode precision (FP32
+and FP64 device results against the oracle's stored values).
 """
 from __future__ import annotations
 
@@ -49,12 +53,20 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "warm", "copy", "precision", "kernels",
-                             "field", "field_kernels", "query", "quad10d", "local"])
+    ap.add_argument("--mode", default="mix",
+                    choices=["mix", "mix_kernels", "step", "batch", "serve", "warm", "copy",
+                             "precision", "kernels", "field", "field_kernels", "query", "quad10d",
+                             "local"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="mix mode: oracle processes (0 = the host cores this process may "
+                         "use, at most 16)")
+    ap.add_argument("--profile-steps", type=int, default=128,
+                    help="mix mode: RK2 steps of the profiled 4-D pass")
+    ap.add_argument("--copy-mib", type=int, default=2048, help="copy mode: MiB per copy")
     ap.add_argument("--chunk", type=int, default=None, help="RK2 steps per chunk (default: autotuned)")
     ap.add_argument("--levels", type=int, default=2, help="1 = cold fine grid only")
     ap.add_argument("--count", type=int, default=256, help="batch mode: problems")
@@ -69,6 +81,213 @@ def progress(msg):
 
 def pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+# ---------------------------------------------------------------------------
+# mix (default): 256 independent subsystem solves in one batched solve
+# ---------------------------------------------------------------------------
+
+def host_cpu():
+    """CPU model and core counts of the host this process runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return dict(model=model, nproc=os.cpu_count(), usable=usable)
+
+
+def _oracle_worker(job):
+    """One oracle process: RK2 steps of one problem of the mix from its cold
+    start, single thread, until `seconds` have passed (at least one step)."""
+    entry, seconds = job
+    from oracle import oracle as O
+    from paper_2101_05916_amd import workloads as W
+    P = W.problem_from_manifest(entry)
+    g = O.make_grid(P.n, P.lo, P.hi)
+    d = O.make_dyn(P.kind, P.params)
+    alpha = O.lf_alpha(d, g, P.dlo, P.dhi)
+    dt = O.dt(g, alpha)
+    V = P.l.copy()
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        V, _ = O.iterate(d, g, P.dlo, P.dhi, alpha, dt, P.l, V)
+        steps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    return P.size * steps, steps, time.perf_counter() - t0, entry["n"]
+
+
+def mix_cpu_baseline(seconds, workers, W, count):
+    """The oracle as it stands on a bounded sample of the mix: one process per
+    usable host core (at most 16), each running RK2 steps of one 4-D problem
+    of the mix (the first `workers` of them, in manifest order) for
+    `seconds`.  Runs before this process touches the GPU (the workers are
+    forked)."""
+    import multiprocessing as mp
+    cpu = host_cpu()
+    n = workers if workers > 0 else min(16, cpu["usable"] or 1)
+    man = [e for e in W.batch_manifest(count, seed=0) if e["kind"] == W.QUAD_X4D][:n]
+    n = len(man)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(n) as pool:
+        res = pool.map(_oracle_worker, [(e, seconds) for e in man])
+    wall = time.perf_counter() - t0
+    rates = [r[0] / r[2] for r in res]
+    # the processes run side by side: their rates add up
+    return dict(value=float(sum(rates)), unit="cell-updates/s", cores=n, kind="oracle",
+                sample=f"RK2 steps of the first {n} 4-D problems of the mix (sizes "
+                       f"{sorted(r[3] for r in res)}^4), one single-threaded FP64 oracle "
+                       f"process each, {sum(r[1] for r in res)} steps, "
+                       f"{min(r[2] for r in res):.1f}-{max(r[2] for r in res):.1f} s each, "
+                       f"{wall:.1f} s wall; value = sum of the process rates",
+                per_core=float(np.mean(rates)), cpu_model=cpu["model"], nproc=cpu["nproc"],
+                usable_cores=cpu["usable"])
+
+
+def build_mix(torch, hjr, W, count, only_4d=False):
+    """Device inputs of the mix: per problem its spec, l (FP32) and output V."""
+    out = []
+    for e in W.batch_manifest(count, seed=0):
+        if only_4d and e["kind"] != W.QUAD_X4D:
+            continue
+        P = W.problem_from_manifest(e)
+        l = torch.tensor(P.l, dtype=torch.float32, device="cuda")
+        out.append((hjr.Spec.of(P), l, torch.empty_like(l)))
+        P.l = None
+    return out
+
+
+def mix_problems(hjr, mix):
+    return [hjr.make_problem(spec, l, V) for spec, l, V in mix]
+
+
+def profile_mix_4d(torch, hjr, W, count, chunk, steps):
+    """Device time per launch of the dominant kernel, RK stage 2 of the 4-D
+    family, with HIP events on the engine's stream (HJR_FLAG_PROFILE: the
+    stage launches of one chunk in eight, stamped at the kernels' own start
+    and end): the mix's 121 4-D problems batched, their first `steps` RK2
+    steps from the cold start, during which every one of them is live."""
+    mix = build_mix(torch, hjr, W, count, only_4d=True)
+    probs = mix_problems(hjr, mix)
+    hjr.solve_batch(probs, dtype=torch.float32, max_iter=16, chunk=chunk)
+    _, stats = hjr.solve_batch(probs, dtype=torch.float32, max_iter=steps, chunk=chunk,
+                               flags=hjr.FLAG_PROFILE)
+    s = stats[0]
+    nodes = sum(spec.size for spec, _, _ in mix)
+    del probs, mix
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return (np.asarray(s["kernel_ms"]), np.asarray(s["kernel_launches"]),
+            s["kernel_cell_updates"], nodes)
+
+
+def mode_mix(args, torch, hjr, W):
+    mix = build_mix(torch, hjr, W, args.count)
+    n4 = sum(1 for spec, _, _ in mix if len(spec.n) == 4)
+    nodes = sum(spec.size for spec, _, _ in mix)
+    progress(f"mix: {len(mix)} problems ({n4} 4-D), {nodes:.3e} nodes")
+    probs = mix_problems(hjr, mix)
+
+    def run():
+        r, stats = hjr.solve_batch(probs, dtype=torch.float32, chunk=args.chunk)
+        if r != hjr.OK:
+            raise RuntimeError(f"the mix did not converge: {[s['status'] for s in stats]}")
+        return stats
+
+    for i in range(args.warmup):
+        s0 = time.perf_counter()
+        run()
+        progress(f"warm-up step {i + 1}/{args.warmup}: {time.perf_counter() - s0:.2f} s")
+    torch.cuda.synchronize()
+    lat, cu, its = [], 0, None
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        s0 = time.perf_counter()
+        stats = run()
+        lat.append((time.perf_counter() - s0) * 1e3)
+        cu += sum(s["cell_updates"] for s in stats)
+        its = [s["iterations"] for s in stats]
+        progress(f"timed step {i + 1}/{args.steps}: {lat[-1] / 1e3:.2f} s")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    del probs, mix
+    torch.cuda.empty_cache()
+    # dominant kernel: RK stage 2 of the 4-D family reads Vhat, V, l and
+    # writes V (4 x 4 B per cell-update); stage 1 reads V and writes Vhat (8 B)
+    kms, kn, kcu, n4nodes = profile_mix_4d(torch, hjr, W, args.count, args.chunk,
+                                           args.profile_steps)
+    progress(f"profiled pass: stage 1 {kms[0] / max(kn[0], 1) * 1e3:.1f} us, stage 2 "
+             f"{kms[1] / max(kn[1], 1) * 1e3:.1f} us per launch over {n4nodes:.3e} nodes")
+    achieved = kcu * 16.0 / (kms[1] * 1e-3) / 1e9
+    value = cu / el if el > 0 else 0.0
+    out = {
+        "metric": "grid cell-updates/s",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / max(args.steps, 1) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched mix of {args.count} independent subsystem safe-set solves "
+                        "(seed 0): 2-D vertical quadcopter 51^2..201^2 and 4-D x-subsystem "
+                        "31^4..61^4 (p = 1/2 each), dbar ~ U[0.2, 1.0], cold starts, ENO2+LF+"
+                        "TVD-RK2, CFL 0.8, tol 1e-4 (4-D: residual band |V| < 0.5), FP32 "
+                        "values / FP64 residual, one batched solve per step",
+            "problems": args.count,
+            "problems_4d": n4,
+            "nodes": nodes,
+            "cell_updates_per_step": cu / max(args.steps, 1),
+            "iterations_min_max": [min(its), max(its)] if its else None,
+        },
+        "updates_per_s": args.count * args.steps / el if el > 0 else 0.0,
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "hbm_frac_end_to_end": value * 24.0 / (HBM_PEAK_GBS * 1e9),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_stage<float,2,X4D narrow, ENO2> (RK stage 2 + projection + residual), "
+                      f"the mix's {n4} 4-D problems batched ({n4nodes} nodes, all live)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic("mix_stage2"),
+            "bytes_per_cell_update": 16,
+            "avg_launch_us": kms[1] / max(kn[1], 1) * 1e3,
+            "launches_timed": int(kn[1]),
+            "cell_updates_timed": int(kcu),
+            "stage1_avg_launch_us": kms[0] / max(kn[0], 1) * 1e3,
+            "stage1_plus_stage2_GBs": kcu * 24.0 / ((kms[0] + kms[1]) * 1e-3) / 1e9,
+        },
+    }
+    if getattr(args, "cpu_result", None) is not None:
+        out["cpu_baseline"] = args.cpu_result
+    return out
+
+
+def mode_mix_kernels(args, torch, hjr, W):
+    """Only the profiled pass of mix mode (the 121 4-D problems, their first
+    --profile-steps RK2 steps), for kernel traces and counter collection."""
+    kms, kn, kcu, n4nodes = profile_mix_4d(torch, hjr, W, args.count, args.chunk,
+                                           args.profile_steps)
+    return {"mode": "mix_kernels", "nodes": n4nodes, "steps": args.profile_steps,
+            "stage_avg_launch_us": [float(kms[i] / max(kn[i], 1) * 1e3) for i in (0, 1)],
+            "launches_timed": [int(x) for x in kn], "cell_updates_timed": int(kcu)}
 
 
 # ---------------------------------------------------------------------------
@@ -799,7 +1018,7 @@ def mode_kernels(args, torch, hjr, W):
 # ---------------------------------------------------------------------------
 
 def mode_copy(args, torch, hjr, W):
-    nbytes = 256 << 20
+    nbytes = args.copy_mib << 20
     x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
     torch.cuda.synchronize()
@@ -845,14 +1064,21 @@ def main():
         print("bench.py runs on one GPU only: each subsystem solve lives on one device "
               "(multi-GPU sharding is not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    from paper_2101_05916_amd import workloads as W
+    args.cpu_result = None
+    if args.mode == "mix" and not args.no_cpu_baseline:
+        # the oracle processes are forked before this process touches the GPU
+        progress("oracle baseline on the host cores")
+        args.cpu_result = mix_cpu_baseline(args.cpu_seconds, args.cpu_workers, W, args.count)
+        progress(f"oracle: {args.cpu_result['value']:.3e} cell-updates/s on "
+                 f"{args.cpu_result['cores']} cores")
     import torch
     from paper_2101_05916_amd import hjr
-    from paper_2101_05916_amd import workloads as W
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     hjr.lib()
-    fn = {"step": mode_step, "batch": mode_batch, "serve": mode_serve, "warm": mode_warm,
+    fn = {"mix": mode_mix, "mix_kernels": mode_mix_kernels, "step": mode_step, "batch": mode_batch, "serve": mode_serve, "warm": mode_warm,
           "copy": mode_copy, "precision": mode_precision, "kernels": mode_kernels,
           "field": mode_field, "field_kernels": mode_field_kernels, "query": mode_query,
           "quad10d": mode_quad10d, "local": mode_local}[args.mode]
