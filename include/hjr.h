@@ -201,6 +201,30 @@ hjr_status hjr_solve_ex(const hjr_dyn* dyn, const hjr_grid* grid, const void* l,
                         const void* V0, const hjr_dstb* d, double tol,
                         const hjr_opts* o, void* V_out, hjr_stats* stats);
 
+/* Device scratch bytes available to hjr_solve_noalloc per device. */
+#define HJR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* hjr_solve_ex for callers that cannot allocate memory: code that must not
+ * call hipMalloc (tight serving loops, harnesses that forbid allocation).
+ * The stage-1 array, the per-axis table and the iteration tables live in a
+ * statically sized device array of HJR_NOALLOC_SCRATCH_BYTES per device
+ * (loaded with the library, held until the process ends); the host staging
+ * is on the caller's stack.  The call allocates no device or pinned host
+ * memory and creates no stream, event or graph: it runs on o->stream
+ * itself, launching kernel by kernel (hjr_opts.flags other than
+ * HJR_FLAG_FLAT_TILES and hjr_opts.workspace are ignored) and synchronising
+ * that stream after every chunk of o->chunk iterations.  Arguments, results
+ * and statuses as for hjr_solve_ex (stats->device_ms is the call's wall
+ * time); results are bit-identical to hjr_solve_ex's.  ENOMEM, with nothing
+ * enqueued, if the grid needs more scratch than HJR_NOALLOC_SCRATCH_BYTES
+ * (about N elements of the dtype: up to ~16.7e6 FP32 or ~8.3e6 FP64 nodes).
+ * Every call on one device shares that device's scratch: calls that overlap
+ * on one device (from several threads or streams) race and must not be
+ * issued; sequential calls are independent (nothing is carried over). */
+hjr_status hjr_solve_noalloc(const hjr_dyn* dyn, const hjr_grid* grid, const void* l,
+                             const void* V0, const hjr_dstb* d, double tol,
+                             const hjr_opts* o, void* V_out, hjr_stats* stats);
+
 /* Level transition of the coarse-to-fine scheme (paper Sec. III-C): sample
  * V_src (grid src) onto grid dst by multilinear interpolation.  For
  * destination index j of axis i: num = j (n_src - 1), q = num div

@@ -18,6 +18,13 @@
 
 using namespace hjr;
 
+// Scratch of hjr_solve_noalloc: one statically sized array per device,
+// loaded with the code object and held until the process ends.  In host
+// code `scratch` names a host-side stand-in, not device memory: only the
+// address from hipGetSymbolAddress (per device, with that device current)
+// may be handed to kernels or copies.
+static __device__ __align__(256) char scratch[HJR_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr int kDefaultChunk = 32;
@@ -348,6 +355,32 @@ hjr_status solve_levels_impl(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* g
     }
 }
 
+// Per-device address of the scratch of hjr_solve_noalloc (file scope, above).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (looked up once per device).
+hjr_status scratch_of_current_device(void** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HJR_EDEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return HJR_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return HJR_EDEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HJR_OK;
+}
+
+// Host staging of a static engine with one slot: at most this many bytes
+// (host_bytes(1, kMaxChunk)), on the caller's stack.
+constexpr size_t kNoallocHostBytes = 16384;
+
 }  // namespace
 
 extern "C" {
@@ -471,6 +504,69 @@ hjr_status hjr_solve(const hjr_dyn* dyn, const hjr_grid* grid, const void* l, co
         if (residual) *residual = st.residual;
     }
     return r;
+}
+
+hjr_status hjr_solve_noalloc(const hjr_dyn* dyn, const hjr_grid* grid, const void* l,
+                            const void* V0, const hjr_dstb* d, double tol, const hjr_opts* o,
+                            void* V_out, hjr_stats* stats)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    const hjr_opts op = resolve(o);
+    if (!opts_valid(op)) return HJR_EINVAL;
+    hjr_status st = check_job_spec(dyn, 1, grid, d, tol, op.band);
+    if (st != HJR_OK) return st;
+    if (!l || !V_out) return HJR_EINVAL;
+    const int K = chunk_of(op);
+    const int64_t N = grid_size(*grid);
+    const int64_t n2 = grid->ndim >= 3 ? grid->n[2] : 1;
+    const size_t tables = align256(Engine::table_bytes(1, K));
+    const size_t need = tables + align256(N * elem_size(op.dtype)) +
+                        align256(n2 * elem_size(op.dtype));
+    if (need > (size_t)HJR_NOALLOC_SCRATCH_BYTES) return HJR_ENOMEM;
+    if (Engine::host_bytes(1, K) > kNoallocHostBytes) return HJR_EINVAL;
+    void* base = nullptr;
+    if ((st = scratch_of_current_device(&base)) != HJR_OK) return st;
+    alignas(256) char host_stage[kNoallocHostBytes];
+    try {
+        EngineCfg cfg;
+        cfg.dtype = op.dtype;
+        cfg.order = op.order;
+        cfg.cfl = op.cfl;
+        cfg.max_iter = op.max_iter;
+        cfg.K = K;
+        cfg.cap = 1;
+        // graphs, pipelining and profiling need objects the static mode
+        // does not create; the tile choice is kept
+        cfg.flags = op.flags & HJR_FLAG_FLAT_TILES;
+        Engine eng(cfg);
+        if ((st = eng.init_static((hipStream_t)op.stream, base, host_stage)) != HJR_OK) return st;
+        Job j;
+        j.dyn = *dyn;
+        std::memset(j.d, 0, sizeof(j.d));
+        for (int c = 0; c < dyn_channels(dyn->kind); c++) j.d[c] = d[c];
+        j.tol = tol;
+        j.band = op.band;
+        j.nlev = 1;
+        j.lev[0].grid = *grid;
+        j.lev[0].l = l;
+        j.lev[0].V = V_out;
+        j.lev[0].tile_rows = op.tile_rows;
+        j.V0 = V0;
+        j.Vhat = (char*)base + tables;
+        j.table = (char*)j.Vhat + align256(N * elem_size(op.dtype));
+        if ((st = eng.add(&j)) != HJR_OK) return st;
+        if ((st = run_engine(eng)) != HJR_OK) return st;
+        ProbState ps;
+        if ((st = eng.read_state(j.slot, &ps)) != HJR_OK) return st;
+        const double ms = std::chrono::duration<double, std::milli>(
+                              std::chrono::steady_clock::now() - t_start).count();
+        fill_stats(stats, j, ps, ms, eng);
+        return (hjr_status)j.status;
+    } catch (const std::bad_alloc&) {
+        return HJR_ENOMEM;
+    } catch (...) {
+        return HJR_EDEVICE;
+    }
 }
 
 hjr_status hjr_batch_workspace_bytes(int32_t n, const hjr_problem* probs, const hjr_opts* o,

@@ -141,9 +141,11 @@ Engine::~Engine()
         if (f.ev) (void)hipEventDestroy(f.ev);
     for (int p = 0; p < 2; p++) {
         for (auto& g : graphs_[p]) (void)hipGraphExecDestroy(g.second);
-        if (h_desc_[p]) (void)hipHostFree(h_desc_[p]);
-        if (h_ctl_[p]) (void)hipHostFree(h_ctl_[p]);
-        if (h_compact_[p]) (void)hipHostFree(h_compact_[p]);
+        if (!static_) {
+            if (h_desc_[p]) (void)hipHostFree(h_desc_[p]);
+            if (h_ctl_[p]) (void)hipHostFree(h_ctl_[p]);
+            if (h_compact_[p]) (void)hipHostFree(h_compact_[p]);
+        }
         if (desc_ev_[p]) (void)hipEventDestroy(desc_ev_[p]);
         for (hipEvent_t e : prof_ev_[p]) (void)hipEventDestroy(e);
     }
@@ -164,7 +166,25 @@ size_t Engine::table_bytes(int cap, int K)
     return b;
 }
 
-hjr_status Engine::init(hipStream_t stream, void* arena)
+size_t Engine::host_bytes(int cap, int K)
+{
+    if (K > kMaxChunk) K = kMaxChunk;
+    const size_t desc = (sizeof(ProbDesc) + sizeof(int64_t) + sizeof(int32_t)) * cap;
+    return 2 * (align256(desc) + align256(256 + sizeof(ProbCtl) * cap) +
+                align256(sizeof(double) * (size_t)cap * K));
+}
+
+hjr_status Engine::init_static(hipStream_t stream, void* dev_arena, void* host_arena)
+{
+    if (!dev_arena || !host_arena) return HJR_EINVAL;
+    static_ = true;
+    depth_ = 0;
+    profile_ = false;
+    use_graph_ = false;
+    return init(stream, dev_arena, host_arena);
+}
+
+hjr_status Engine::init(hipStream_t stream, void* arena, void* host_arena)
 {
     stream_ = stream;
     const int cap = cfg_.cap, K = cfg_.K;
@@ -196,15 +216,31 @@ hjr_status Engine::init(hipStream_t stream, void* arena)
     d_mask_counts_ = (uint64_t*)take(sizeof(uint64_t) * 4 * cap);
     d_check_ = (uint64_t*)take(sizeof(uint64_t));
 
+    char* hp = (char*)host_arena;
+    auto take_host = [&](size_t bytes) {
+        char* r = hp;
+        hp += align256(bytes);
+        return (void*)r;
+    };
     for (int q = 0; q < 2; q++) {
-        HJR_TRY(hipHostMalloc((void**)&h_desc_[q], desc_bytes_, hipHostMallocDefault));
-        HJR_TRY(hipHostMalloc((void**)&h_ctl_[q], ctl_bytes_, hipHostMallocDefault));
-        HJR_TRY(hipHostMalloc((void**)&h_compact_[q], sizeof(double) * (size_t)cap * K,
-                              hipHostMallocDefault));
+        if (static_) {
+            // caller's host memory (pageable): every copy from or to it is
+            // waited for before the host touches it again (depth 0)
+            h_desc_[q] = (ProbDesc*)take_host(desc_bytes_);
+            h_ctl_[q] = (char*)take_host(ctl_bytes_);
+            h_compact_[q] = (double*)take_host(sizeof(double) * (size_t)cap * K);
+        } else {
+            HJR_TRY(hipHostMalloc((void**)&h_desc_[q], desc_bytes_, hipHostMallocDefault));
+            HJR_TRY(hipHostMalloc((void**)&h_ctl_[q], ctl_bytes_, hipHostMallocDefault));
+            HJR_TRY(hipHostMalloc((void**)&h_compact_[q], sizeof(double) * (size_t)cap * K,
+                                  hipHostMallocDefault));
+        }
         std::memset(h_desc_[q], 0, desc_bytes_);
         std::memset(h_ctl_[q], 0, ctl_bytes_);
-        HJR_TRY(hipEventCreateWithFlags(&desc_ev_[q], hipEventDisableTiming));
-        HJR_TRY(hipEventRecord(desc_ev_[q], stream_));
+        if (!static_) {
+            HJR_TRY(hipEventCreateWithFlags(&desc_ev_[q], hipEventDisableTiming));
+            HJR_TRY(hipEventRecord(desc_ev_[q], stream_));
+        }
     }
     // zero the residual histories and mask counters once
     for (int q = 0; q < 2; q++)
@@ -457,7 +493,7 @@ hjr_status Engine::upload_table()
 {
     const int q = desc_par_;
     desc_par_ ^= 1;
-    HJR_TRY(hipEventSynchronize(desc_ev_[q]));  // staging q no longer being read
+    if (desc_ev_[q]) HJR_TRY(hipEventSynchronize(desc_ev_[q]));  // staging q no longer being read
     const int cap = cfg_.cap;
     ProbDesc* h = h_desc_[q];
     int64_t* tb = (int64_t*)(h + cap);
@@ -495,7 +531,7 @@ hjr_status Engine::upload_table()
     fam_pos_[kNumFam] = pos;
     total_tiles_ = total;
     HJR_TRY(hipMemcpyAsync(d_desc_, h, desc_bytes_, hipMemcpyHostToDevice, stream_));
-    HJR_TRY(hipEventRecord(desc_ev_[q], stream_));
+    if (desc_ev_[q]) HJR_TRY(hipEventRecord(desc_ev_[q], stream_));
     table_dirty_ = false;
     return HJR_OK;
 }
@@ -665,8 +701,10 @@ hjr_status Engine::step()
     }
     HJR_TRY(hipMemcpyAsync(h_compact_[par], d_compact_[par], sizeof(double) * (size_t)cap * K,
                            hipMemcpyDeviceToHost, stream_));
-    HJR_TRY(hipEventCreateWithFlags(&f.ev, hipEventDisableTiming));
-    HJR_TRY(hipEventRecord(f.ev, stream_));
+    if (!static_) {
+        HJR_TRY(hipEventCreateWithFlags(&f.ev, hipEventDisableTiming));
+        HJR_TRY(hipEventRecord(f.ev, stream_));
+    }  // (static mode: depth 0, process() synchronises the stream instead)
     flights_.push_back(std::move(f));
     chunk_++;
     while ((int)flights_.size() > depth_) {
@@ -691,8 +729,8 @@ hjr_status Engine::drain()
 
 hjr_status Engine::process(Flight& f)
 {
-    hipError_t e = hipEventSynchronize(f.ev);
-    (void)hipEventDestroy(f.ev);
+    hipError_t e = f.ev ? hipEventSynchronize(f.ev) : hipStreamSynchronize(stream_);
+    if (f.ev) (void)hipEventDestroy(f.ev);
     f.ev = nullptr;
     if (e != hipSuccess) {
         last_err_ = e;

@@ -81,7 +81,18 @@ public:
 
     // Bind to a stream (the engine enqueues everything there) and place the
     // tables in `arena` (table_bytes) or allocate them when arena is null.
-    hjr_status init(hipStream_t stream, void* arena);
+    hjr_status init(hipStream_t stream, void* arena, void* host_arena = nullptr);
+
+    // Bytes of host memory the engine's staging buffers take for cap slots.
+    static size_t host_bytes(int cap, int K);
+
+    // Static mode, for callers that cannot allocate: the device tables go to
+    // dev_arena (table_bytes), the host staging buffers to host_arena
+    // (host_bytes, ordinary memory), and the engine creates no stream, event
+    // or graph and allocates no device or pinned memory; it runs without
+    // graphs, profiling or pipelining, synchronising its stream after every
+    // chunk.
+    hjr_status init_static(hipStream_t stream, void* dev_arena, void* host_arena);
 
     // Make an idle engine ready for a new set of jobs: takes order, cfl and
     // max_iter from c (dtype, K, cap and flags must match the engine's).
@@ -131,8 +142,8 @@ public:
 
 private:
     struct Flight {
-        int64_t chunk;
-        hipEvent_t ev;
+        int64_t chunk = 0;
+        hipEvent_t ev = nullptr;    // completion event (none in static mode)
         bool timed = false;         // stage launches bracketed by events
         std::vector<Job*> job;      // per slot, job that ran (or null)
         std::vector<int> limit;     // per slot
@@ -171,6 +182,7 @@ private:
     int fam_grid_[2][kNumFam] = {};  // workgroup cap per stage and family (occupancy x CUs)
     int fam_grid_big_[kNumFam] = {};  // stage 2's cap when the family's values exceed HJR_BIG_SET_BYTES
     bool own_arena_ = false;
+    bool static_ = false;  // init_static: nothing allocated, nothing created
     void* arena_ = nullptr;
     // device tables: problem descriptors, then the family order list (first
     // tile per position, slot per position)

@@ -27,7 +27,7 @@ EXPORTS = (
     "hjr_solve_batch", "hjr_server_create", "hjr_server_submit", "hjr_server_poll",
     "hjr_server_wait", "hjr_server_read_value", "hjr_server_memory", "hjr_server_destroy",
     "hjr_solve_field", "hjr_safety_query", "hjr_safety_query_decomposed", "hjr_band_mask",
-    "hjr_solve_local",
+    "hjr_solve_local", "hjr_solve_noalloc",
 )
 
 
@@ -143,6 +143,9 @@ def lib() -> C.CDLL:
     L.hjr_solve_ex.restype = st
     L.hjr_solve_ex.argtypes = [P(Dyn), P(Grid), C.c_void_p, C.c_void_p, P(Dstb), C.c_double,
                                P(Opts), C.c_void_p, P(Stats)]
+    L.hjr_solve_noalloc.restype = st
+    L.hjr_solve_noalloc.argtypes = [P(Dyn), P(Grid), C.c_void_p, C.c_void_p, P(Dstb),
+                                    C.c_double, P(Opts), C.c_void_p, P(Stats)]
     L.hjr_interp.restype = st
     L.hjr_interp.argtypes = [P(Grid), C.c_void_p, P(Grid), C.c_void_p, C.c_void_p, P(Opts)]
     L.hjr_refine_mask.restype = st
@@ -376,6 +379,41 @@ def solve(spec: Spec, l, V0=None, V_out=None, *, dtype=None, order=2, cfl=0.8,
     out = st.as_dict()
     out["return"] = r
     return V_out, out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # HJR_NOALLOC_SCRATCH_BYTES
+
+
+def solve_noalloc(spec: Spec, l, V_out, V0=None, *, order=2, cfl=0.8, max_iter=100000,
+                  chunk=None, tile_rows=None, flags=0, check=True):
+    """hjr_solve_noalloc: the solve of `solve` (constant bounds, one level)
+    without any allocation in the library; l, V_out (and V0) are the
+    caller's device tensors of spec.size elements, all of one dtype.  Runs
+    on torch's current stream.  Returns (status, stats dict); raises
+    HjrError unless the status is OK or NOT_CONVERGED (check=False returns
+    any status)."""
+    torch = _torch()
+    dtype = l.dtype
+    if chunk is None or tile_rows is None:
+        t = tuned(spec.kind, dtype, spec.n)
+        chunk = t.get("chunk", 0) if chunk is None else chunk
+        tile_rows = t.get("tile_rows", 0) if tile_rows is None else tile_rows
+    N = spec.size
+    _check_tensor(l, N, dtype, "l")
+    _check_tensor(V_out, N, dtype, "V_out")
+    if V0 is not None:
+        _check_tensor(V0, N, dtype, "V0")
+    o = make_opts(dtype, order, cfl, max_iter, chunk, flags, tile_rows=tile_rows, band=spec.band,
+                  stream=torch.cuda.current_stream(l.device))
+    st = Stats()
+    g = make_grid(spec.n, spec.lo, spec.hi)
+    dyn = make_dyn(spec.kind, spec.params)
+    d = make_dstb(spec.dlo, spec.dhi)
+    r = lib().hjr_solve_noalloc(C.byref(dyn), C.byref(g), _ptr(l), _ptr(V0), d, spec.tol,
+                                C.byref(o), _ptr(V_out), C.byref(st))
+    if check:
+        _raise(r, "hjr_solve_noalloc", (OK, NOT_CONVERGED))
+    return r, st.as_dict()
 
 
 def band_mask(spec: Spec, V, k: int):
