@@ -20,6 +20,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 FP64_TOL = 5e-5
+FP64_STEP_TOL = 1e-10  # fixed runs of <= 30 steps: the two evaluation orders agree to rounding
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -119,7 +120,7 @@ def test_masked_solve_fixed_steps(case, dt):
     err = float(np.max(np.abs(V.cpu().numpy().astype(np.float64) - ref["V"])))
     print(f"masked {kind} {shape}{' field' if field else ''} {dt}: max|dV| {err:.3e}")
     assert st["iterations"] == ref["iterations"] == steps
-    assert err <= (FP64_TOL if dt == "f64" else 1e-4)
+    assert err <= (FP64_STEP_TOL if dt == "f64" else 1e-4)
 
 
 def test_empty_mask_stops_at_once():

@@ -30,6 +30,12 @@ pytestmark = pytest.mark.gpu
 # evaluation-order change perturbs every operation, so the bar allows an
 # order of magnitude more and stays below the FP32 bar.
 FP64_TOL = 5e-5
+# FP64 runs of a fixed, small number of steps (<= 40 ENO2 steps, or first-order
+# steps, which make no stencil choice): too few steps for a stencil flip to be
+# likely, so the two evaluation orders agree to rounding, ~1e-14 (13^4 band
+# solve: 1.6e-14; 21^4 after 40 steps: ~1e-14).  A constant wrong at the 1e-6
+# level fails this bar.
+FP64_STEP_TOL = 1e-10
 
 torch = pytest.importorskip("torch")
 
@@ -118,7 +124,9 @@ def test_x4d_fp64_21_steps40():
     assert _ulps(st["dt"], ref["dt"]) <= 4
     for a in range(4):
         assert _ulps(st["alpha"][a], ref["alpha"][a]) <= 4
-    assert np.max(np.abs(V - ref["V"])) <= FP64_TOL
+    err = float(np.max(np.abs(V - ref["V"])))
+    print(f"x4d 21^4 fp64 40 steps: max|dV| {err:.3e}")
+    assert err <= FP64_STEP_TOL
 
 
 def test_x4d_fp32_21_steps40():
@@ -135,7 +143,9 @@ def test_x4d_fp64_ragged_shape():
     ref = oracle_solve(P, max_iter=25)
     V, st = device_solve(P, torch.float64, max_iter=25)
     assert st["iterations"] == ref["iterations"] == 25
-    assert np.max(np.abs(V - ref["V"])) <= FP64_TOL
+    err = float(np.max(np.abs(V - ref["V"])))
+    print(f"x4d ragged fp64 25 steps: max|dV| {err:.3e}")
+    assert err <= FP64_STEP_TOL
 
 
 @pytest.mark.parametrize("perm", [(0, 1, 2, 3), (3, 1, 0, 2), (2, 0, 1, 3)])
@@ -145,7 +155,13 @@ def test_di2x2_fp64_axis_permutations(perm):
     P = W.di2x2((11, 12, 13, 14), perm=perm)
     ref = oracle_solve(P, max_iter=30)
     V, st = device_solve(P, torch.float64, max_iter=30)
-    assert np.max(np.abs(V - ref["V"])) <= FP64_TOL
+    err = float(np.max(np.abs(V - ref["V"])))
+    print(f"di2x2 {perm} fp64 30 steps: max|dV| {err:.3e}")
+    # the two copies of the vertical model give second differences of equal
+    # magnitude in many places, where ENO2's choice flips on rounding: with
+    # the coordinates on axes (0, 1, 2, 3) the device and the oracle differ
+    # by 1.1e-7 after 30 steps (6.7e-15 in the other two layouts)
+    assert err <= FP64_TOL
 
 
 def test_minimal_grid_n3():
@@ -161,7 +177,9 @@ def test_first_order_matches_oracle():
     ref = oracle_solve(P, order=1, max_iter=300)
     V, st = device_solve(P, torch.float64, order=1, max_iter=300)
     assert st["iterations"] == ref["iterations"]
-    assert np.max(np.abs(V - ref["V"])) <= FP64_TOL
+    err = float(np.max(np.abs(V - ref["V"])))
+    print(f"z2d 41^2 first order fp64 {st['iterations']} steps: max|dV| {err:.3e}")
+    assert err <= FP64_STEP_TOL
 
 
 # ---------------------------------------------------------------- every tile family
@@ -186,7 +204,7 @@ def test_tile_families_match_oracle(case, dt):
     err = float(np.max(np.abs(V - ref["V"])))
     print(f"{kind} {shape} order {order} {dt}: {steps} steps, max|dV| {err:.3e}")
     assert st["iterations"] == ref["iterations"] == steps
-    assert err <= (FP64_TOL if dt == "f64" else 1e-4)
+    assert err <= (FP64_STEP_TOL if dt == "f64" else 1e-4)
 
 
 # ---------------------------------------------------------------- warm start
@@ -301,4 +319,6 @@ def test_flat_tiles_match_oracle(shape, kind):
     for flags in (0, hjr.FLAG_FLAT_TILES):
         V, st = device_solve(P, torch.float64, max_iter=30, flags=flags)
         assert st["iterations"] == 30
-        assert np.max(np.abs(V - ref["V"])) <= FP64_TOL
+        err = float(np.max(np.abs(V - ref["V"])))
+        print(f"{kind} {shape} flags {flags} fp64 30 steps: max|dV| {err:.3e}")
+        assert err <= FP64_STEP_TOL

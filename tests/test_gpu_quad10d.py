@@ -26,6 +26,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 FP64_TOL = 5e-5
+FP64_STEP_TOL = 1e-10  # fixed runs of <= 30 steps: the two evaluation orders agree to rounding
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -73,7 +74,7 @@ def test_x4dv_families_match_oracle(case, dt):
           f"max|dV| {err:.3e}")
     assert st["iterations"] == ref["iterations"] == steps
     assert np.allclose(st["alpha"][:4], ref["alpha"], rtol=1e-6)
-    assert err <= (FP64_TOL if dt == "f64" else 1e-4)
+    assert err <= (FP64_STEP_TOL if dt == "f64" else 1e-4)
 
 
 @pytest.mark.parametrize("field", [False, True])
