@@ -15,8 +15,9 @@ Bars, per level:
     every node): <= 0.1 % of the nodes;
   * max |V - V_oracle| over the nodes the stop test covers (every node, or
     those with |V_oracle| < band for the band rule), against the stored
-    values (the oracle's rounded to float32, +-2.4e-7): FP64 <= FP64_BAR;
-    FP32: the measured error is printed and held to FP32_BAR.  The stored
+    values (the oracle's rounded to float32, +-2.4e-7): FP64 <= FP64_BAR
+    over every node; FP32: the measured error is printed and held to
+    FP32_BAR.  The stored
     levels of 41^4 and 61^4 in the 61^4 chains are samples of 2^18 nodes.
 
 Why FP32 is held to a looser bar than the benchmark spec's 1e-4 here: the scheme's
@@ -81,7 +82,7 @@ def steps_ok(dev, ref, tail, dtype):
     return any(abs(r - TOL) <= 1e-3 * TOL for r in tail[-2:])
 
 
-CASES = ["x4d_chain_d05", "x4d_mix5_31_band"]
+CASES = ["x4d_chain_d05", "x4d_mix5_31_band", "x4d_c2f_d05_band", "x4d_upd_d08_band"]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
@@ -121,7 +122,9 @@ def test_converged_4d_against_oracle(name, dtype):
             failures.append(f"level {k}: steps {dev_steps} vs {ref_steps}")
         if zl > ZERO_LEVEL_BAR:
             failures.append(f"level {k}: zero-level disagreement {zl}")
-        bar = FP64_BAR if dtype == torch.float64 else FP32_BAR
-        if err_cov > bar:
-            failures.append(f"level {k}: max|dV| {err_cov} > {bar}")
+        if dtype == torch.float64:
+            if err_all > FP64_BAR:
+                failures.append(f"level {k}: max|dV| {err_all} > {FP64_BAR}")
+        elif err_cov > FP32_BAR:
+            failures.append(f"level {k}: max|dV| {err_cov} > {FP32_BAR}")
     assert not failures, failures
