@@ -68,6 +68,9 @@ def parse():
                     help="mix mode: RK2 steps of the profiled 4-D pass")
     ap.add_argument("--copy-mib", type=int, default=2048, help="copy mode: MiB per copy")
     ap.add_argument("--chunk", type=int, default=None, help="RK2 steps per chunk (default: autotuned)")
+    ap.add_argument("--walk", type=int, default=0,
+                    help="4-D narrow-plane problems: axis-0 planes per walking workgroup "
+                         "(0 or -1 = plane tiles, the default)")
     ap.add_argument("--levels", type=int, default=2, help="1 = cold fine grid only")
     ap.add_argument("--count", type=int, default=256, help="batch mode: problems")
     ap.add_argument("--requests", type=int, default=3000, help="serve mode: requests")
@@ -171,7 +174,7 @@ def mix_problems(hjr, mix):
     return [hjr.make_problem(spec, l, V) for spec, l, V in mix]
 
 
-def profile_mix_4d(torch, hjr, W, count, chunk, steps):
+def profile_mix_4d(torch, hjr, W, count, chunk, steps, walk=0):
     """Device time per launch of the dominant kernel, RK stage 2 of the 4-D
     family, with HIP events on the engine's stream (HJR_FLAG_PROFILE: the
     stage launches of one chunk in eight, stamped at the kernels' own start
@@ -179,9 +182,9 @@ def profile_mix_4d(torch, hjr, W, count, chunk, steps):
     steps from the cold start, during which every one of them is live."""
     mix = build_mix(torch, hjr, W, count, only_4d=True)
     probs = mix_problems(hjr, mix)
-    hjr.solve_batch(probs, dtype=torch.float32, max_iter=16, chunk=chunk)
+    hjr.solve_batch(probs, dtype=torch.float32, max_iter=16, chunk=chunk, walk=walk)
     _, stats = hjr.solve_batch(probs, dtype=torch.float32, max_iter=steps, chunk=chunk,
-                               flags=hjr.FLAG_PROFILE)
+                               flags=hjr.FLAG_PROFILE, walk=walk)
     s = stats[0]
     nodes = sum(spec.size for spec, _, _ in mix)
     del probs, mix
@@ -199,7 +202,8 @@ def mode_mix(args, torch, hjr, W):
     probs = mix_problems(hjr, mix)
 
     def run():
-        r, stats = hjr.solve_batch(probs, dtype=torch.float32, chunk=args.chunk)
+        r, stats = hjr.solve_batch(probs, dtype=torch.float32, chunk=args.chunk,
+                                   walk=args.walk)
         if r != hjr.OK:
             raise RuntimeError(f"the mix did not converge: {[s['status'] for s in stats]}")
         return stats
@@ -225,7 +229,7 @@ def mode_mix(args, torch, hjr, W):
     # dominant kernel: RK stage 2 of the 4-D family reads Vhat, V, l and
     # writes V (4 x 4 B per cell-update); stage 1 reads V and writes Vhat (8 B)
     kms, kn, kcu, n4nodes = profile_mix_4d(torch, hjr, W, args.count, args.chunk,
-                                           args.profile_steps)
+                                           args.profile_steps, args.walk)
     progress(f"profiled pass: stage 1 {kms[0] / max(kn[0], 1) * 1e3:.1f} us, stage 2 "
              f"{kms[1] / max(kn[1], 1) * 1e3:.1f} us per launch over {n4nodes:.3e} nodes")
     achieved = kcu * 16.0 / (kms[1] * 1e-3) / 1e9
@@ -284,8 +288,8 @@ def mode_mix_kernels(args, torch, hjr, W):
     """Only the profiled pass of mix mode (the 121 4-D problems, their first
     --profile-steps RK2 steps), for kernel traces and counter collection."""
     kms, kn, kcu, n4nodes = profile_mix_4d(torch, hjr, W, args.count, args.chunk,
-                                           args.profile_steps)
-    return {"mode": "mix_kernels", "nodes": n4nodes, "steps": args.profile_steps,
+                                           args.profile_steps, args.walk)
+    return {"mode": "mix_kernels", "walk": args.walk, "nodes": n4nodes, "steps": args.profile_steps,
             "stage_avg_launch_us": [float(kms[i] / max(kn[i], 1) * 1e3) for i in (0, 1)],
             "launches_timed": [int(x) for x in kn], "cell_updates_timed": int(kcu)}
 

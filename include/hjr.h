@@ -127,7 +127,12 @@ typedef struct hjr_opts {
     int32_t tile_rows;      /* rows of the two fastest axes per LDS tile (a
                                tuning knob, see paper_2101_05916_amd/autotune.py);
                                0 = library default.  Clamped to what fits. */
-    int32_t reserved;
+    int32_t walk;           /* 4-D problems on narrow LDS planes (last axis
+                               <= 64 nodes, no per-node bounds): consecutive
+                               axis-0 planes one workgroup walks through per
+                               tile (a tuning knob; results do not depend on
+                               it); 0 (default) or -1 = none (plane tiles one
+                               by one), k >= 1 = k */
     double band;            /* residual band of the stop test (see above);
                                0 (default) = every node; must be >= 0 */
 } hjr_opts;

@@ -50,6 +50,7 @@ bool opts_valid(const hjr_opts& o)
     if (o.max_iter < 1) return false;
     if (o.chunk < 0 || o.chunk > kMaxChunk) return false;
     if (o.tile_rows < 0) return false;
+    if (o.walk < -1) return false;
     if (!(o.band >= 0.0)) return false;
     return true;
 }
@@ -295,6 +296,7 @@ hjr_status solve_levels_impl(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* g
         cfg.order = op.order;
         cfg.cfl = op.cfl;
         cfg.max_iter = op.max_iter;
+        cfg.walk = op.walk;
         cfg.K = K;
         cfg.cap = 1;
         cfg.flags = op.flags;
@@ -533,6 +535,7 @@ hjr_status hjr_solve_noalloc(const hjr_dyn* dyn, const hjr_grid* grid, const voi
         cfg.order = op.order;
         cfg.cfl = op.cfl;
         cfg.max_iter = op.max_iter;
+        cfg.walk = op.walk;
         cfg.K = K;
         cfg.cap = 1;
         // graphs, pipelining and profiling need objects the static mode
@@ -610,6 +613,7 @@ hjr_status hjr_solve_batch(int32_t n, const hjr_problem* probs, const hjr_opts* 
         cfg.order = op.order;
         cfg.cfl = op.cfl;
         cfg.max_iter = op.max_iter;
+        cfg.walk = op.walk;
         cfg.K = K;
         cfg.cap = n;
         cfg.flags = op.flags;

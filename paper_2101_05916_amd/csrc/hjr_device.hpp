@@ -24,7 +24,7 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #define HJR_NODE_UNROLL 2            // nodes of a lane whose loads are issued together
 #endif
 #ifndef HJR_BLOCKS_PER_CU
-#define HJR_BLOCKS_PER_CU 24         // cap on stage workgroups per CU (6 single-wave groups per SIMD)
+#define HJR_BLOCKS_PER_CU 20         // cap on stage workgroups per CU (5 single-wave groups per SIMD)
 #endif
 #ifndef HJR_BLOCKS_PER_CU_S2
 #define HJR_BLOCKS_PER_CU_S2 20      // cap for the FP32 stage-2 kernels (0: HJR_BLOCKS_PER_CU); the
@@ -39,6 +39,12 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #define HJR_BLOCKS_PER_CU_F64 14     // the same for the FP64 kernels (15, which their LDS
                                      // allows, measured 17-20 % slower)
 #endif
+#ifndef HJR_I0_BLOCK
+#define HJR_I0_BLOCK 4               // 4-D plane tiles: axis-0 indices per block of the plane order
+#endif
+#ifndef HJR_STAGE_DMA
+#define HJR_STAGE_DMA 3              // plane tiles staged by direct global-to-LDS loads: bit 0
+#endif                               // stage 1, bit 1 stage 2 (else through registers)
 #ifndef HJR_WAVES_PER_EU
 #define HJR_WAVES_PER_EU 0           // occupancy hint for the stage kernels, 0 = none
 #endif
@@ -63,11 +69,17 @@ constexpr int kProfileEvery = 8;     // HJR_FLAG_PROFILE times one chunk in this
 constexpr int kRowStrideS = 72;      // planes whose last axis has <= 68 nodes
 constexpr int kRowStrideL = 208;     // planes whose last axis has <= 204 nodes
 constexpr int kPlaneNodesPT = HJR_PLANE_NODES_PT;   // nodes per thread of a plane tile
-constexpr int kPlaneStagePT = 2 * kPlaneNodesPT;    // staged elements per thread of a plane tile
+constexpr int kPlaneStagePT = 2 * kPlaneNodesPT;    // staged elements per thread (register staging)
 constexpr int kPlaneElemsS = 18 * kRowStrideS;  // LDS elements of a narrow block (<= 14 rows)
 constexpr int kPlaneElemsL = 8 * kRowStrideL;   // LDS elements of a wide block (<= 4 rows)
+// Walking plane tiles: at most this many rows per tile (so the staged rows,
+// tile rows + 4 halo rows, fit the prefetch registers) and columns (a lane
+// per column).
+constexpr int kWalkRows = 12;
+constexpr int kWalkStageRows = kWalkRows + 4;
+constexpr int kWalkMaxCols = 64;
 
-enum TilePath : int32_t { kPathFlat = 0, kPathPlaneS = 1, kPathPlaneL = 2 };
+enum TilePath : int32_t { kPathFlat = 0, kPathPlaneS = 1, kPathPlaneL = 2, kPathWalk = 3 };
 
 // Tile families.  Every family has its own stage kernels, so registers and
 // LDS are sized for its tile code alone; a chunk launches one kernel per
@@ -82,13 +94,21 @@ enum Family : int32_t {
     kFamZ2dS1, kFamZ2dL1, kFamX4dS1, kFamX4dL1,
     kFamZ2dS2F, kFamZ2dL2F, kFamX4dS2F, kFamX4dL2F,
     kFamXvS2, kFamXvL2, kFamXvS2F, kFamXvL2F,  // QUAD_X4DV
+    kFamX4dW2, kFamX4dW1, kFamXvW2,            // walking tiles (narrow planes)
     kNumFam
 };
+
+__host__ __device__ constexpr bool fam_walk(int f)
+{
+    return f >= kFamX4dW2 && f <= kFamXvW2;
+}
 
 // Model of a plane family (HJR_QUAD_Z2D, HJR_QUAD_X4D, HJR_QUAD_X4DV; -1 flat).
 __host__ __device__ constexpr int fam_model(int f)
 {
     return f == kFamFlat ? -1
+         : f == kFamX4dW2 || f == kFamX4dW1 ? HJR_QUAD_X4D
+         : f == kFamXvW2 ? HJR_QUAD_X4DV
          : f >= kFamXvS2 ? HJR_QUAD_X4DV
          : (((f - 1) & 3) >= 2 ? HJR_QUAD_X4D : HJR_QUAD_Z2D);
 }
@@ -97,12 +117,12 @@ __host__ __device__ constexpr int fam_model(int f)
 // (Z2D S, Z2D L, X4D S, X4D L) and in the QUAD_X4DV group (S, L, S, L).
 __host__ __device__ constexpr int fam_rs(int f)
 {
-    return f == kFamFlat ? 0 : (((f - 1) & 1) ? kRowStrideL : kRowStrideS);
+    return f == kFamFlat ? 0 : f >= kFamX4dW2 ? kRowStrideS : (((f - 1) & 1) ? kRowStrideL : kRowStrideS);
 }
 
 __host__ __device__ constexpr int fam_order(int f)
 {
-    return (f >= kFamZ2dS1 && f <= kFamX4dL1) ? 1 : 2;
+    return ((f >= kFamZ2dS1 && f <= kFamX4dL1) || f == kFamX4dW1) ? 1 : 2;
 }
 
 __host__ __device__ constexpr bool fam_x4d(int f)  // a 4-D model
@@ -112,13 +132,21 @@ __host__ __device__ constexpr bool fam_x4d(int f)  // a 4-D model
 
 __host__ __device__ constexpr bool fam_field(int f)
 {
-    return (f >= kFamZ2dS2F && f <= kFamX4dL2F) || f >= kFamXvS2F;
+    return (f >= kFamZ2dS2F && f <= kFamX4dL2F) || f == kFamXvS2F || f == kFamXvL2F;
 }
 
 // LDS elements of a plane block of row stride rs (0 for flat tiles).
 __host__ __device__ constexpr int plane_elems(int rs)
 {
     return rs == kRowStrideS ? kPlaneElemsS : rs == kRowStrideL ? kPlaneElemsL : 0;
+}
+
+// Whether plane tiles of RK stage `stage` stage their rows by direct
+// global-to-LDS loads (else through registers, with a spare LDS slot per
+// lane after the block).
+__host__ __device__ constexpr bool stage_by_dma(int stage)
+{
+    return ((HJR_STAGE_DMA >> (stage - 1)) & 1) != 0;
 }
 
 // Division of a 31-bit unsigned index by a runtime divisor d >= 2 with one
@@ -130,7 +158,7 @@ struct FastDiv {
     uint32_t d;
     uint32_t m;
     uint32_t s;
-    uint32_t pad;
+    uint32_t m20;  // ceil(2^20 / d): x / d = (x * m20) >> 20 for x * d < 2^20 (24-bit multiplies)
 };
 
 // Static description of one problem in the batch (written by the host).
@@ -171,6 +199,24 @@ struct ProbDesc {
     const uint8_t* tmask;    // with umask: per flat tile, whether it holds a node to update
     int64_t tile_begin;      // first global tile of this problem
     int64_t ntiles;
+    // walking plane tiles (4-D narrow planes, last axis <= 64 nodes): a
+    // tile walks `walk` consecutive indices of axis 0 (0 = plane tiles one
+    // by one); nseg = ceil(n[0] / walk)
+    int32_t walk;
+    int32_t nseg;
+    int32_t wslab;           // axis-1 slabs per walking tile (1, or 2 when 2 (n[3] + 4) <= 72)
+    int32_t ngroups;         // ceil(n[1] / wslab)
+    FastDiv div_groups;      // divisor ngroups
+    // 4-D plane tiles: order of the (i0, i1) planes, in blocks of bx
+    // consecutive axis-0 indices (bx <= 1: i1 fastest); nblk = ceil(n[0] /
+    // bx) blocks, the last one of bxl indices
+    int32_t bx;
+    int32_t nblk;
+    int32_t bxl;
+    float band_f;            // band rounded up to a float: for a float x, x >= band iff x >= band_f
+    FastDiv div_bxn1;        // divisor bx * n[1]
+    FastDiv div_bx;          // divisor bx
+    FastDiv div_bxl;         // divisor bxl (when >= 2)
 };
 
 // The stage kernels address the tables they only read (problem descriptors,
@@ -187,6 +233,8 @@ typedef const HJR_CONST ProbDesc PDesc;
 inline int family_of(const ProbDesc& P)
 {
     if (P.path == kPathFlat) return kFamFlat;
+    if (P.path == kPathWalk)
+        return P.kind == HJR_QUAD_X4DV ? kFamXvW2 : (P.order == 1 ? kFamX4dW1 : kFamX4dW2);
     const bool narrow = P.path == kPathPlaneS;
     if (P.kind == HJR_QUAD_X4DV) return (P.dfield ? kFamXvS2F : kFamXvS2) + (narrow ? 0 : 1);
     const bool x4 = P.kind == HJR_QUAD_X4D;
@@ -221,7 +269,8 @@ struct ChunkHdr {
     int64_t fam_tile[kNumFam + 1];
     int32_t fam_pos[kNumFam + 1];
 };
-static_assert(sizeof(ChunkHdr) <= 256, "ChunkHdr must fit its 256-byte slot");
+constexpr int kHdrBytes = 512;  // device slot of the chunk header, before the ProbCtl array
+static_assert(sizeof(ChunkHdr) <= kHdrBytes, "ChunkHdr must fit its slot");
 
 struct ProbCtl {
     int32_t limit;   // iterations this problem may take in this chunk (0..K)

@@ -107,6 +107,7 @@ FastDiv make_fastdiv(uint32_t d)
     const uint64_t num = uint64_t(1) << (32 + s);
     f.m = (uint32_t)((num + d - 1) / d);
     f.s = s;
+    f.m20 = d < (1u << 20) ? (uint32_t)(((1u << 20) + d - 1) / d) : 0;
     return f;
 }
 
@@ -158,7 +159,7 @@ size_t Engine::table_bytes(int cap, int K)
     size_t b = 0;
     b += align256((sizeof(ProbDesc) + sizeof(int64_t) + sizeof(int32_t)) * cap);
     b += align256(sizeof(ProbState) * cap);
-    b += 2 * align256(256 + sizeof(ProbCtl) * cap);
+    b += 2 * align256(kHdrBytes + sizeof(ProbCtl) * cap);
     b += 2 * align256(sizeof(uint64_t) * (size_t)cap * (K + 1) * kResSubs);
     b += 2 * align256(sizeof(double) * (size_t)cap * K);
     b += align256(sizeof(uint64_t) * 4 * cap);
@@ -170,7 +171,7 @@ size_t Engine::host_bytes(int cap, int K)
 {
     if (K > kMaxChunk) K = kMaxChunk;
     const size_t desc = (sizeof(ProbDesc) + sizeof(int64_t) + sizeof(int32_t)) * cap;
-    return 2 * (align256(desc) + align256(256 + sizeof(ProbCtl) * cap) +
+    return 2 * (align256(desc) + align256(kHdrBytes + sizeof(ProbCtl) * cap) +
                 align256(sizeof(double) * (size_t)cap * K));
 }
 
@@ -206,10 +207,10 @@ hjr_status Engine::init(hipStream_t stream, void* arena, void* host_arena)
     d_tb_ = (int64_t*)(d_desc_ + cap);
     d_ord_ = (int32_t*)(d_tb_ + cap);
     d_state_ = (ProbState*)take(sizeof(ProbState) * cap);
-    ctl_bytes_ = 256 + sizeof(ProbCtl) * cap;
+    ctl_bytes_ = kHdrBytes + sizeof(ProbCtl) * cap;
     for (int q = 0; q < 2; q++) {
         d_hdr_[q] = (ChunkHdr*)take(ctl_bytes_);
-        d_ctl_[q] = (ProbCtl*)((char*)d_hdr_[q] + 256);
+        d_ctl_[q] = (ProbCtl*)((char*)d_hdr_[q] + kHdrBytes);
     }
     for (int q = 0; q < 2; q++) d_res_[q] = (uint64_t*)take(sizeof(uint64_t) * (size_t)cap * (K + 1) * kResSubs);
     for (int q = 0; q < 2; q++) d_compact_[q] = (double*)take(sizeof(double) * (size_t)cap * K);
@@ -289,6 +290,7 @@ hjr_status Engine::reset(const EngineCfg& c)
     cfg_.order = c.order;
     cfg_.cfl = c.cfl;
     cfg_.max_iter = c.max_iter;
+    cfg_.walk = c.walk;
     for (auto& f : flights_)
         if (f.ev) (void)hipEventDestroy(f.ev);
     flights_.clear();
@@ -332,7 +334,7 @@ int Engine::free_slots() const
     return n;
 }
 
-void Engine::fill_desc(const Job* j, ProbDesc& P) const
+void Engine::fill_desc(const Job* j, ProbDesc& P, int walk) const
 {
     std::memset(&P, 0, sizeof(P));
     const Level& L = j->lev[j->cur];
@@ -357,6 +359,11 @@ void Engine::fill_desc(const Job* j, ProbDesc& P) const
     }
     P.tol = j->tol;
     P.band = j->band > 0.0 ? j->band : HUGE_VAL;
+    {
+        float bf = (float)P.band;
+        if ((double)bf < P.band) bf = std::nextafter(bf, HUGE_VALF);
+        P.band_f = bf;
+    }
     P.cfl = cfg_.cfl;
     P.V = L.V;
     P.l = L.l;
@@ -427,10 +434,15 @@ void Engine::fill_desc(const Job* j, ProbDesc& P) const
             P.path = kPathPlaneL;
         }
         if (rs) {
-            // rows per tile: at most kPlaneNodesPT nodes and kPlaneStagePT
-            // staged elements per thread, and the LDS block within plane_elems
+            // walking tiles: 4-D models without per-node bounds on narrow
+            // planes of at most kWalkMaxCols columns
+            const bool walks = walk > 0 && D == 4 && rs == kRowStrideS && nc <= kWalkMaxCols &&
+                               !P.dfield && P.kind != HJR_DI2X2;
+            // rows per tile: at most kPlaneNodesPT nodes per thread, and the
+            // LDS block within plane_elems
             int want = std::min(plane_elems(rs) / rs - 4, kPlaneNodesPT * kStageBlock / nc);
-            want = std::min(want, kPlaneStagePT * kStageBlock / nc - 4);
+            // (a walking tile holds a column per lane, not nodes per thread)
+            if (walks) want = std::min(plane_elems(rs) / rs - 4, kWalkRows);
             if (L.tile_rows > 0) want = std::min(want, L.tile_rows);
             want = std::max(want, 1);
             const int chunks = (nr + want - 1) / want;
@@ -441,6 +453,27 @@ void Engine::fill_desc(const Job* j, ProbDesc& P) const
             int64_t outer = 1;
             for (int a = 0; a < D - 2; a++) outer *= g.n[a];
             P.ntiles = outer * chunks;
+            if (D == 4 && !walks && HJR_I0_BLOCK > 1 && g.n[0] > 1) {
+                const int bx = std::min<int>(HJR_I0_BLOCK, g.n[0]);
+                P.bx = bx;
+                P.nblk = (g.n[0] + bx - 1) / bx;
+                P.bxl = g.n[0] - (P.nblk - 1) * bx;
+                P.div_bxn1 = make_fastdiv((uint32_t)(bx * g.n[1]));
+                P.div_bx = make_fastdiv((uint32_t)bx);
+                P.div_bxl = make_fastdiv((uint32_t)std::max(P.bxl, 2));
+            }
+            if (walks) {
+                const int w = std::min(walk, g.n[0]);
+                P.walk = w;
+                P.nseg = (g.n[0] + w - 1) / w;
+                // two axis-1 slabs side by side in a workgroup's lanes and LDS
+                // rows when both fit
+                P.wslab = (2 * nc <= kStageBlock && 2 * (nc + 4) <= rs) ? 2 : 1;
+                P.ngroups = (g.n[1] + P.wslab - 1) / P.wslab;
+                P.div_groups = make_fastdiv((uint32_t)std::max(P.ngroups, 2));
+                P.ntiles = (int64_t)P.ngroups * chunks * P.nseg;
+                P.path = kPathWalk;
+            }
         }
     }
 }
@@ -499,10 +532,15 @@ hjr_status Engine::upload_table()
     int64_t* tb = (int64_t*)(h + cap);
     int32_t* ord = (int32_t*)(tb + cap);
     std::vector<int> fam_of(cap, -1);
+    // Walking tiles only on request (walk >= 1): on the FP32 stage kernels
+    // they measured slower than the plane tiles for every narrow-plane size
+    // tried, the one-column-per-lane mapping leaving lanes idle when the last
+    // axis has 33..63 nodes.
+    const int walk = cfg_.walk > 0 ? cfg_.walk : 0;
     for (int s = 0; s < cap; s++) {
         Job* j = slots_[s];
         if (j && !j->done) {
-            fill_desc(j, h[s]);
+            fill_desc(j, h[s], walk);
             if (h[s].ntiles > 0) fam_of[s] = family_of(h[s]);
         } else {
             std::memset(&h[s], 0, sizeof(ProbDesc));
@@ -630,7 +668,7 @@ hjr_status Engine::step()
     f.limit.assign(cap, 0);
     f.sched.assign(cap, 0);
     ChunkHdr* hdr = (ChunkHdr*)h_ctl_[par];
-    ProbCtl* ctl = (ProbCtl*)(h_ctl_[par] + 256);
+    ProbCtl* ctl = (ProbCtl*)(h_ctl_[par] + kHdrBytes);
     hdr->total_tiles = total_tiles_;
     hdr->nprob = cap;
     for (int f = 0; f <= kNumFam; f++) {

@@ -32,6 +32,7 @@ struct EngineCfg {
     int cap = 1;       // problem slots
     int flags = 0;
     int grid = 0;      // workgroups per iteration kernel; 0 = from occupancy
+    int walk = 0;      // hjr_opts.walk: 0 = automatic, -1 = none, k >= 1 = k planes
 };
 
 struct Level {
@@ -158,7 +159,9 @@ private:
     hjr_status build_graph(int par, hipGraphExec_t* out);
     hjr_status process(Flight& f);
     void finish_level(Job* j, int status, int64_t iters, double residual);
-    void fill_desc(const Job* j, ProbDesc& P) const;
+    // walk: axis-0 planes per walking tile for the problems that can take
+    // them, 0 = plane tiles one by one
+    void fill_desc(const Job* j, ProbDesc& P, int walk = 0) const;
     ChunkArgs args(int par, int slot) const;
 
     // Stage launches of the current chunk: family and workgroups per stage.

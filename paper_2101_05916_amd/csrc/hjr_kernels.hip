@@ -131,9 +131,9 @@ __device__ __forceinline__ void flush_residual(const ChunkArgs& A, int p, uint64
 template <typename T, int STAGE, int FAM>
 __global__ __launch_bounds__(kStageBlock) HJR_STAGE_ATTR void k_stage(ChunkArgs A)
 {
-    // a plane block and one spare slot per lane (lanes past the end of a
-    // tile stage into their spare slot)
-    constexpr int kElems = FAM == kFamFlat ? 4 : plane_elems(fam_rs(FAM)) + kStageBlock;
+    // a plane block (and a spare slot per lane for staging through registers)
+    constexpr int kElems = FAM == kFamFlat ? 4
+                                           : plane_elems(fam_rs(FAM)) + (stage_by_dma(STAGE) ? 0 : kStageBlock);
     __shared__ uint64_t red[kStageBlock / 64];
     __shared__ __align__(16) char smem[kElems * sizeof(T)];
     T* lds = (T*)smem;
@@ -532,6 +532,9 @@ static hipError_t launch_stage_t(hipStream_t s, int fam, const ChunkArgs& a, int
     case kFamXvL2: launch_one<T, STAGE, kFamXvL2>(s, g, b, a, e0, e1); break;
     case kFamXvS2F: launch_one<T, STAGE, kFamXvS2F>(s, g, b, a, e0, e1); break;
     case kFamXvL2F: launch_one<T, STAGE, kFamXvL2F>(s, g, b, a, e0, e1); break;
+    case kFamX4dW2: launch_one<T, STAGE, kFamX4dW2>(s, g, b, a, e0, e1); break;
+    case kFamX4dW1: launch_one<T, STAGE, kFamX4dW1>(s, g, b, a, e0, e1); break;
+    case kFamXvW2: launch_one<T, STAGE, kFamXvW2>(s, g, b, a, e0, e1); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -795,6 +798,9 @@ static const void* stage_kernel(int fam)
     case kFamXvS2: return (const void*)k_stage<T, STAGE, kFamXvS2>;
     case kFamXvL2: return (const void*)k_stage<T, STAGE, kFamXvL2>;
     case kFamXvS2F: return (const void*)k_stage<T, STAGE, kFamXvS2F>;
+    case kFamX4dW2: return (const void*)k_stage<T, STAGE, kFamX4dW2>;
+    case kFamX4dW1: return (const void*)k_stage<T, STAGE, kFamX4dW1>;
+    case kFamXvW2: return (const void*)k_stage<T, STAGE, kFamXvW2>;
     default: return (const void*)k_stage<T, STAGE, kFamXvL2F>;
     }
 }

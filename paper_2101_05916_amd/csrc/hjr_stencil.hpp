@@ -32,6 +32,24 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t x, const HJR_CONST FastDiv& f)
     return __umulhi(x, f.m) >> f.s;
 }
 
+// x / f.d for x * f.d < 2^20 (both factors below 2^24): a 24-bit multiply
+// and a shift, full-rate instructions, where fdiv takes a quarter-rate
+// 32-bit multiply-high.
+__device__ __forceinline__ uint32_t fdiv20(uint32_t x, const HJR_CONST FastDiv& f)
+{
+    return __umul24(x, f.m20) >> 20;
+}
+
+// Pins a loop-invariant value in a vector register: an operand pair of two
+// scalar registers (a select between two constants, an fma of a node
+// coordinate with two constants) would otherwise cost a copy per node.
+template <typename T>
+__device__ __forceinline__ T in_vgpr(T x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // Global-memory access through an explicit global address space: the
 // problem table hands out generic pointers, and a generic (flat) access both
 // costs a 64-bit address add per load and counts against the LDS wait
@@ -245,20 +263,33 @@ struct HamX4D {
         E = hc[8];
         n0s = hc[9];
         gts = (const T*)P.table;
+        // operands that would meet another scalar operand in one per-node
+        // instruction (the select between dl and dh, the fma bases A and D)
+        dl = in_vgpr(dl);
+        dh = in_vgpr(dh);
+        A = in_vgpr(A);
+        D = in_vgpr(D);
     }
     // table[j2], loaded by plane tiles together with the node's other loads
     __device__ __forceinline__ T row_coef(int j2) const { return ld32(gts, (uint32_t)j2); }
-    __device__ __forceinline__ T eval(const T* sum, int j0, int j1, int j2, int j3, T g) const
+    // the node-coordinate terms: (0.5/h0) vx, (0.5/h2)(omega - d1 theta) and
+    // (0.5/h3) d0 theta
+    __device__ __forceinline__ T coef_vx(int j1) const { return c0 + (T)j1 * c1; }
+    __device__ __forceinline__ T coef_tw(int j2, int j3) const { return A + (T)j3 * B - (T)j2 * C; }
+    __device__ __forceinline__ T coef_t3(int j2) const { return D + (T)j2 * E; }
+    // H from the per-axis sums and the node's terms (g: the row coefficient)
+    __device__ __forceinline__ T eval_terms(const T* sum, T cvx, T tw, T t3, T g) const
     {
-        const T cvx = c0 + (T)j1 * c1;                   // (0.5/h0) vx
-        const T tw = A + (T)j3 * B - (T)j2 * C;          // (0.5/h2)(omega - d1 theta)
-        const T t3 = D + (T)j2 * E;                      // (0.5/h3) d0 theta
         const T s0 = sum[0], s1 = sum[1];
         if (VD)
             return s0 * cvx + s1 * (g + (s1 >= T(0) ? dl : dh)) + sum[2] * tw - sum[3] * t3 +
                    n0s * fabs(sum[3]);
         return s0 * (cvx + (s0 >= T(0) ? dl : dh)) + s1 * g + sum[2] * tw - sum[3] * t3 +
                n0s * fabs(sum[3]);
+    }
+    __device__ __forceinline__ T eval(const T* sum, int j0, int j1, int j2, int j3, T g) const
+    {
+        return eval_terms(sum, coef_vx(j1), coef_tw(j2, j3), coef_t3(j2), g);
     }
     __device__ __forceinline__ T operator()(const T* sum, int j0, int j1, int j2, int j3) const
     {
@@ -397,11 +428,16 @@ __device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b)
 
 // Whether a node enters the residual: unless both the old and the new value
 // lie at or beyond the band (band = +inf counts every node; a NaN counts).
-// The test runs in double on the stored values.
-template <typename T>
-__device__ __forceinline__ bool in_band(T vn, T vo, double band)
+// FP32 values compare with the band rounded up to a float, which decides
+// exactly as the comparison in double would.
+__device__ __forceinline__ bool in_band(double vn, double vo, PDesc& P)
 {
-    return !(fabs((double)vn) >= band && fabs((double)vo) >= band);
+    return !(fabs(vn) >= P.band && fabs(vo) >= P.band);
+}
+
+__device__ __forceinline__ bool in_band(float vn, float vo, PDesc& P)
+{
+    return !(fabsf(vn) >= P.band_f && fabsf(vo) >= P.band_f);
 }
 
 // Stage 1 writes Vhat = c + dt L.  Stage 2 writes V' = min(l, (V + c + dt L)/2)
@@ -419,7 +455,7 @@ __device__ __forceinline__ void finish_node(PDesc& P, int64_t gi, T c, T L, T dt
         const T lv = ld64((const T*)P.l, gi);
         const T vn = (lv < avg) ? lv : avg;
         st64((T*)P.V, gi, vn);
-        if (in_band(vn, vo, P.band)) rmax = umax64(rmax, dbits(fabs((double)vn - (double)vo)));
+        if (in_band(vn, vo, P)) rmax = umax64(rmax, dbits(fabs((double)vn - (double)vo)));
     }
 }
 
@@ -496,10 +532,44 @@ __device__ __forceinline__ void clamped_offsets(int j, int n, int s, int* o)
 }
 
 // Stage the loaded rows of a plane tile (nlr rows of nc nodes from element
-// load0) into LDS rows lrow.. of stride RS, columns at +2: element e = lane +
+// load0) into LDS rows lrow.. of stride RS, columns at +2, by direct
+// global-to-LDS loads: one load instruction per row and 64-dword segment,
+// lane i copying dword d0 + i of the row to the dword at the same position
+// of the LDS row (a load of this kind writes its 64 dwords to consecutive LDS
+// addresses from a wave-uniform base).  The staging costs no vector
+// instructions and holds no registers.  A row of W <= 64 dwords is one
+// segment whose lanes past the end copy its last dword to the dwords after
+// the row, still inside the row's stride (2 elements + 64 dwords <= RS
+// elements); longer rows take segments at 0, 64, ... and a last one ending
+// at the row's end, so no lane writes outside the row.  The columns after
+// the row are the ghost columns, written after the loads have completed.
+template <typename T, int RS>
+__device__ __forceinline__ void stage_dma(const T* in, uint32_t load0, int nc, int nlr, int lrow, T* lds,
+                                          int tid)
+{
+    static_assert(2 * sizeof(T) + 64 * 4 <= RS * sizeof(T), "a one-segment row stays in its stride");
+    constexpr int kRowDw = RS * (int)sizeof(T) / 4;  // LDS row stride in dwords
+    constexpr int kCol0 = 2 * (int)sizeof(T) / 4;    // dword of column 0 in an LDS row
+    const int W = nc * (int)sizeof(T) / 4;           // dwords of a row
+    const int nseg = (W + 63) >> 6;
+    const HJR_GLOBAL char* src = (const HJR_GLOBAL char*)in + (size_t)load0 * sizeof(T);
+    __attribute__((address_space(3))) char* dst =
+        (__attribute__((address_space(3))) char*)lds + (size_t)(lrow * kRowDw + kCol0) * 4;
+    for (int sg = 0; sg < nseg; sg++) {
+        const int d0 = (sg == nseg - 1 && sg > 0) ? W - 64 : 64 * sg;
+        const uint32_t voff = (uint32_t)min(d0 + tid, W - 1) * 4u;
+        for (int r = 0; r < nlr; r++)
+            __builtin_amdgcn_global_load_lds(
+                (const HJR_GLOBAL void*)(src + (size_t)r * (size_t)W * 4 + voff),
+                (__attribute__((address_space(3))) void*)(dst + (r * kRowDw + d0) * 4), 4, 0, 0);
+    }
+}
+
+// Stage the same rows through registers: element e = lane +
 // 64 k of the loaded rows goes to LDS row e / nc, column e mod nc (one
 // multiply-high division).  All loads are issued before the first LDS write;
-// lanes past the end load a clamped element and write it to their spare slot.
+// lanes past the end load a clamped element and write it to their spare slot
+// (plane_elems(RS) + lane).
 // (Staging column by column instead -- lane c owns column c, no division --
 // executed more vector instructions in total and ran slower.)
 template <typename T, int RS>
@@ -521,27 +591,26 @@ __device__ __forceinline__ void stage_flat(const T* in, uint32_t load0, int nc, 
     for (int k = 0; k < kPlaneStagePT; k++) {
         if (k * kStageBlock < nload) {
             const int e = tid + k * kStageBlock;
-            const int rr = (int)fdiv((uint32_t)e, div_nc);
-            const int cc = e - rr * nc;
-            lds[e < nload ? (lrow + rr) * RS + cc + 2 : kSpare + tid] = sv[k];
+            const int rr = (int)fdiv20((uint32_t)e, div_nc);
+            const int cc = e - (int)__umul24((uint32_t)rr, (uint32_t)nc);
+            lds[e < nload ? (int)__umul24((uint32_t)(lrow + rr), (uint32_t)RS) + cc + 2 : kSpare + tid] = sv[k];
         }
     }
 }
 
+
 // Tile t of a problem covers rows [r0, r1) of axis D-2 at a fixed index of
 // the outer axes (i0, i1 for D = 4); the host keeps (r1 - r0) * n_last <=
-// kPlaneNodesPT * kStageBlock, (r1 - r0 + 4) * n_last <= kPlaneStagePT *
-// kStageBlock and (r1 - r0 + 4) * RS <= plane_elems(RS).  The rows r0-2 ..
-// r1+1 that exist are loaded in one batch into an LDS block with columns
+// kPlaneNodesPT * kStageBlock and (r1 - r0 + 4) * RS <= plane_elems(RS).
+// The rows r0-2 .. r1+1 that exist are loaded in one batch into an LDS block with columns
 // -2 .. n_last+1 (stride RS); the missing rows and the columns past the ends
 // receive the ghost extrapolations, so every in-plane neighbour is a
 // constant LDS offset.  The outer-axis neighbours of a node (and in stage 2
 // its V and l) come straight from global memory, issued together per node.
 //
-// The staging and the node loop run without divergent branches: a lane past
-// the end loads a clamped index, and its LDS write goes to a spare slot
-// (plane_elems(RS) + lane) or its result is dropped; only uniform tests
-// skip whole groups of 64.
+// The node loop runs without divergent branches: a lane past the end
+// computes the tile's last node again and drops its result; only uniform
+// tests skip whole groups of 64.
 template <typename T, int D, class Ham, int STAGE, int RS, int ORDER>
 __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
 {
@@ -552,12 +621,31 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
     const int chunk = (int)(tile - outer * (uint32_t)P.chunks);
     int i0 = 0, i1 = 0;
     if (D == 4) {
-        i0 = (int)fdiv(outer, P.div[1]);
-        i1 = (int)outer - i0 * P.n[1];
+        if (P.bx > 1) {
+            // blocked order: blocks of bx consecutive axis-0 indices, axis 1
+            // next, axis 0 fastest inside a block (the last block may be
+            // shorter); workgroups running together then hold a compact
+            // patch of (i0, i1) planes, whose neighbour planes stay in L2
+            const uint32_t blk = fdiv(outer, P.div_bxn1);
+            const int rem = (int)(outer - blk * (uint32_t)(P.bx * P.n[1]));
+            int q, bxs;
+            if ((int)blk == P.nblk - 1) {
+                bxs = P.bxl;
+                q = bxs == 1 ? rem : (int)fdiv((uint32_t)rem, P.div_bxl);
+            } else {
+                bxs = P.bx;
+                q = (int)fdiv((uint32_t)rem, P.div_bx);
+            }
+            i1 = q;
+            i0 = (int)blk * P.bx + (rem - q * bxs);
+        } else {
+            i0 = (int)fdiv(outer, P.div[1]);
+            i1 = (int)outer - i0 * P.n[1];
+        }
     }
     const int r0 = chunk * P.rows;
     const int r1 = min(r0 + P.rows, nr);
-    const uint32_t plane0 = outer * (uint32_t)(nr * nc);
+    const uint32_t plane0 = (uint32_t)(i0 * P.n[1] + i1) * (uint32_t)(nr * nc);
     const int lr0 = max(r0 - 2, 0), lr1 = min(r1 + 2, nr);
     const uint32_t load0 = plane0 + (uint32_t)(lr0 * nc);  // the loaded rows are contiguous
     const int lrow = lr0 - r0 + 2;                         // LDS row of the first loaded row
@@ -581,7 +669,10 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
     }
 
     // ---- LDS block: loaded rows, then ghost columns and ghost rows ----
-    stage_flat<T, RS>(in, load0, nc, lr1 - lr0, lrow, lds, tid, P.div_last);
+    if (stage_by_dma(STAGE))
+        stage_dma<T, RS>(in, load0, nc, lr1 - lr0, lrow, lds, tid);
+    else
+        stage_flat<T, RS>(in, load0, nc, lr1 - lr0, lrow, lds, tid, P.div_last);
     __syncthreads();
     const int nghc = (lr1 - lr0) * 4;
     for (int e = tid; e < nghc; e += kStageBlock) {
@@ -622,12 +713,15 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
 #pragma unroll
     for (int a = 0; a < 4; a++) ah[a] = Prec<T>::ah(S)[a];
     const T dt = Prec<T>::dt(S);
-    const bool edge0 = D == 4 && (i0 < 2 || i0 > P.n[0] - 3);
-    const bool edge1 = D == 4 && (i1 < 2 || i1 > P.n[1] - 3);
+    // whether the tile touches an end of axis 0 / axis 1 (uniform; held as
+    // scalars so that the tests stay scalar branches)
+    const int edge0 = __builtin_amdgcn_readfirstlane(D == 4 && (i0 < 2 || i0 > P.n[0] - 3) ? 1 : 0);
+    const int edge1 = __builtin_amdgcn_readfirstlane(D == 4 && (i1 < 2 || i1 > P.n[1] - 3) ? 1 : 0);
     T* const vout = (T*)(STAGE == 1 ? P.Vhat : P.V);
     const T* const lc = (const T*)P.l;
     uint64_t rmax = 0;
     constexpr int kUnroll = STAGE == 1 ? kNodeUnroll1 : kNodeUnroll2;
+    static_assert(kPlaneNodesPT * kStageBlock * kRowStrideL < (1 << 20), "fdiv20 range");
 #pragma unroll kUnroll
     for (int k = 0; k < kPlaneNodesPT; k++) {
         if (k * kStageBlock < cnt) {
@@ -635,8 +729,8 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
             const int e = min(tid + k * kStageBlock, cnt - 1);
             const bool live = tid + k * kStageBlock < cnt;
             const uint32_t vb = (node0 + (uint32_t)e) * B;
-            const int rr = (int)fdiv((uint32_t)e, P.div_last);
-            const int cc = e - rr * nc;
+            const int rr = (int)fdiv20((uint32_t)e, P.div_last);
+            const int cc = e - (int)__umul24((uint32_t)rr, (uint32_t)nc);
             T w[8];
             if (D == 4) {
 #pragma unroll
@@ -649,7 +743,7 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
                 vo = gld1<T>(vout, vb);
                 lvv = gld1<T>(lc, vb);
             }
-            const T* q = lds + (rr + 2) * RS + cc + 2;
+            const T* q = lds + __umul24((uint32_t)rr, (uint32_t)RS) + cc + (2 * RS + 2);
             const T c = q[0];
             T sum[4], dif;
             eno_sd<T, ORDER>(q[-2 * RS], q[-RS], c, q[RS], q[2 * RS], sum[ra], dif);
@@ -680,11 +774,223 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
                 const T vn = (lvv < avg) ? lvv : avg;
                 if (live) gst1<T>(vn, vout, vb);
                 const uint64_t r = dbits(fabs((double)vn - (double)vo));
-                if (live && in_band(vn, vo, P.band)) rmax = umax64(rmax, r);
+                if (live && in_band(vn, vo, P)) rmax = umax64(rmax, r);
             }
         }
     }
     __syncthreads();  // the LDS block is reused by the next tile
+    return rmax;
+}
+
+// ------------------------------------------------------------------------
+// walking plane tiles (4-D models without per-node bounds, narrow planes
+// whose last axis has <= 64 nodes)
+// ------------------------------------------------------------------------
+
+// A walking tile covers rows [r0, r1) of the (axis 2, axis 3) plane of
+// P.wslab consecutive axis-1 indices i1b.. ("slabs"), over P.walk
+// consecutive axis-0 indices; at each axis-0 index it computes what
+// tile_plane computes for those rows, with the same arithmetic per node.
+// Lane tid holds column c of slab h (tid = h * nc + c; lanes past the last
+// slab repeat its last column and store nothing),
+// and walks down the rows: its in-plane samples are LDS neighbours at fixed
+// offsets, the axis-0 and axis-1 neighbours global loads from uniform base
+// addresses at the node's own offset.  So a node costs no index arithmetic, and
+// the staging of a plane -- lane c loads column c of every row into
+// registers, one row per load, while the previous plane is computed, then
+// writes them to LDS -- none either.  Tiles are numbered chunk fastest, then
+// slab group, then axis-0 run: workgroups running at one time hold
+// neighbouring slabs of the same run, and the axis-0 neighbours a tile reads
+// are planes it staged itself one or two steps before.
+template <typename T, class Ham, int STAGE, int ORDER>
+__device__ uint64_t tile_walk(PDesc& P, PState& S, uint32_t tile, T* lds)
+{
+    constexpr int RS = kRowStrideS;
+    constexpr uint32_t B = sizeof(T);
+    const T* __restrict__ in = (const T*)(STAGE == 1 ? P.V : P.Vhat);
+    T* const vout = (T*)(STAGE == 1 ? P.Vhat : P.V);
+    const T* const lc = (const T*)P.l;
+    const int n0 = P.n[0], n1 = P.n[1], nr = P.n[2], nc = P.n[3];
+    const uint32_t plane = (uint32_t)(nr * nc);   // elements of one (x, i1) plane
+    const uint32_t s0 = (uint32_t)P.stride[0];
+    // tile -> chunk, slab group, axis-0 run
+    const uint32_t rest = P.chunks == 1 ? tile : fdiv(tile, P.div_chunks);
+    const int chunk = (int)(tile - rest * (uint32_t)P.chunks);
+    const uint32_t seg = P.ngroups == 1 ? rest : fdiv(rest, P.div_groups);
+    const int grp = (int)(rest - seg * (uint32_t)P.ngroups);
+    const int i1b = grp * P.wslab;
+    const int nslab = min(P.wslab, n1 - i1b);
+    const int x0 = (int)seg * P.walk, x1 = min(x0 + P.walk, n0);
+    const int r0 = chunk * P.rows;
+    const int r1 = min(r0 + P.rows, nr);
+    const int rt = r1 - r0;
+    const int lr0 = max(r0 - 2, 0), lr1 = min(r1 + 2, nr);
+    const int nlr = lr1 - lr0;                  // staged rows
+    const int lrow = lr0 - r0 + 2;              // LDS row of the first staged row
+    const int cw = nc + 4;                      // LDS columns of one slab
+    const int tid = threadIdx.x;
+
+    // this lane's column (lanes past the last slab repeat its last column
+    // and store nothing)
+    int h = (int)fdiv((uint32_t)tid, P.div_last);
+    int c = tid - h * nc;
+    const bool own = h < nslab;
+    if (!own) {
+        h = nslab - 1;
+        c = nc - 1;
+    }
+    const int i1 = i1b + h;
+    const int lb = h * cw + c + 2;                       // LDS column
+    const uint32_t vl = ((uint32_t)h * plane + (uint32_t)c) * B;  // byte offset from slab i1b
+    // axis-1 neighbours: per-lane byte offsets (clamped; ghost_fix replaces
+    // the samples past the ends)
+    int o1[4];
+    clamped_offsets(i1, n1, (int)plane, o1);
+    const bool edge1_any = i1b < 2 || i1b + nslab > n1 - 2;
+    // (in tiles at an axis-1 end the lanes' neighbour slabs may lie below
+    // slab i1b: their offsets are taken from the start of the axis-0 plane,
+    // where every one is non-negative)
+    uint32_t e1[4];
+#pragma unroll
+    for (int qq = 0; qq < 4; qq++) e1[qq] = ((uint32_t)((int)((uint32_t)i1 * plane) + o1[qq]) + (uint32_t)c) * B;
+
+    Ham ham;
+    ham.init(P);
+    T ah[4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) ah[a] = Prec<T>::ah(S)[a];
+    const T dt = Prec<T>::dt(S);
+    const T cvx = ham.coef_vx(i1);
+
+    // staging registers: staged row r of this lane's column
+    T sv[kWalkStageRows];
+#pragma unroll
+    for (int r = 0; r < kWalkStageRows; r++) sv[r] = T(0);
+    auto prefetch = [&](int x) {
+        const T* src = in + ((uint32_t)x * s0 + (uint32_t)i1b * plane + (uint32_t)(lr0 * nc));
+#pragma unroll
+        for (int r = 0; r < kWalkStageRows; r++)
+            if (r < nlr) sv[r] = gld1<T>(src + r * nc, vl);
+    };
+
+    uint64_t rmax = 0;
+    prefetch(x0);
+    for (int x = x0; x < x1; x++) {
+#pragma unroll
+        for (int r = 0; r < kWalkStageRows; r++)
+            if (r < nlr) lds[(lrow + r) * RS + lb] = sv[r];
+        __syncthreads();
+        // ghost columns -1, -2 and nc, nc + 1 of every staged row of every
+        // slab, one value per lane
+        for (int e = tid; e < 4 * nslab * nlr; e += kStageBlock) {
+            const int t = e >> 2;
+            const int hh = nslab == 2 ? (t & 1) : 0;
+            const int rr = nslab == 2 ? (t >> 1) : t;
+            T* row = lds + (lrow + rr) * RS + hh * cw + 2;
+            const bool right = (e & 2) != 0, far = (e & 1) != 0;
+            const T v0 = row[right ? nc - 1 : 0], v1v = row[right ? nc - 2 : 1];
+            row[right ? nc + (e & 1) : -1 - (e & 1)] = far ? T(3) * v0 - T(2) * v1v : T(2) * v0 - v1v;
+        }
+        // ghost rows: each lane its own column
+        if (r0 - 2 < 0) {
+            const T v0 = lds[(2 - r0) * RS + lb], v1v = lds[(3 - r0) * RS + lb];
+            lds[(1 - r0) * RS + lb] = T(2) * v0 - v1v;                      // row -1
+            if (r0 == 0) lds[(0 - r0) * RS + lb] = T(3) * v0 - T(2) * v1v;  // row -2
+        }
+        if (r1 + 2 > nr) {
+            const T v0 = lds[(nr + 1 - r0) * RS + lb], v1v = lds[(nr - r0) * RS + lb];
+            lds[(nr - r0 + 2) * RS + lb] = T(2) * v0 - v1v;                                // row nr
+            if (r1 == nr) lds[(nr + 1 - r0 + 2) * RS + lb] = T(3) * v0 - T(2) * v1v;       // row nr + 1
+        }
+        __syncthreads();
+        // the next plane's rows are in flight while this one is computed
+        if (x + 1 < x1) prefetch(x + 1);
+
+        const uint32_t pl = (uint32_t)x * s0 + (uint32_t)i1b * plane;  // slab i1b at x
+        int o0[4];
+        clamped_offsets(x, n0, (int)s0, o0);
+        const bool edge0 = x < 2 || x > n0 - 3;
+        const T* const row0 = in + pl;                 // slab i1b, plane x, row 0
+        const T* const xp = in + (uint32_t)x * s0;     // axis-0 plane x
+        T* const out0 = vout + pl;
+        const T* const l0 = lc + pl;
+        // the global operands of one row of this lane's column
+        struct RowLoads {
+            T w[8];
+            T vo, lv;
+        };
+        auto load_row = [&](int k, RowLoads& R) {
+            // byte offset of the node (row r0 + k) from row0, computed here so
+            // that every access is SGPR base + VGPR offset
+            const uint32_t vr = vl + (uint32_t)((r0 + k) * nc) * B;
+#pragma unroll
+            for (int qq = 0; qq < 4; qq++) R.w[qq] = gld1<T>(row0 + o0[qq], vr);
+            if (edge1_any) {
+                // per-lane clamped axis-1 offsets (the slabs of the tile may
+                // sit on either side of an end)
+                const uint32_t ro = (uint32_t)((r0 + k) * nc) * B;
+#pragma unroll
+                for (int qq = 0; qq < 4; qq++) R.w[4 + qq] = gld1<T>(xp, e1[qq] + ro);
+            } else {
+                const int p1s = (int)plane;
+                R.w[4] = gld1<T>(row0 - 2 * p1s, vr);
+                R.w[5] = gld1<T>(row0 - p1s, vr);
+                R.w[6] = gld1<T>(row0 + p1s, vr);
+                R.w[7] = gld1<T>(row0 + 2 * p1s, vr);
+            }
+            R.vo = R.lv = T(0);
+            if (STAGE == 2) {
+                R.vo = gld1<T>(out0, vr);
+                R.lv = gld1<T>(l0, vr);
+            }
+        };
+        auto compute_row = [&](int k, const RowLoads& R) {
+            const uint32_t vr = vl + (uint32_t)((r0 + k) * nc) * B;
+            const T* q = lds + (k + 2) * RS + lb;
+            const T cv = q[0];
+            T sum[4], dif;
+            eno_sd<T, ORDER>(q[-2 * RS], q[-RS], cv, q[RS], q[2 * RS], sum[2], dif);
+            T L = ah[2] * dif;
+            eno_sd<T, ORDER>(q[-2], q[-1], cv, q[1], q[2], sum[3], dif);
+            L += ah[3] * dif;
+            T m2 = R.w[0], m1 = R.w[1], p1 = R.w[2], p2 = R.w[3];
+            if (edge0) ghost_fix<T>(x, n0, cv, m2, m1, p1, p2);
+            eno_sd<T, ORDER>(m2, m1, cv, p1, p2, sum[0], dif);
+            L += ah[0] * dif;
+            m2 = R.w[4];
+            m1 = R.w[5];
+            p1 = R.w[6];
+            p2 = R.w[7];
+            if (edge1_any) ghost_fix<T>(i1, n1, cv, m2, m1, p1, p2);
+            eno_sd<T, ORDER>(m2, m1, cv, p1, p2, sum[1], dif);
+            L += ah[1] * dif;
+            L += ham.eval_terms(sum, cvx, ham.coef_tw(r0 + k, c), ham.coef_t3(r0 + k),
+                                ham.row_coef(r0 + k));
+            if (STAGE == 1) {
+                if (own) gst1<T>(cv + dt * L, out0, vr);
+            } else {
+                const T vt = cv + dt * L;
+                const T avg = T(0.5) * (R.vo + vt);
+                const T vn = (R.lv < avg) ? R.lv : avg;
+                if (own) gst1<T>(vn, out0, vr);
+                const uint64_t r = dbits(fabs((double)vn - (double)R.vo));
+                if (in_band(vn, R.vo, P)) rmax = umax64(rmax, r);
+            }
+        };
+        // rows in pairs: a row's loads are issued before the previous row
+        // is computed
+        RowLoads ra, rb;
+        load_row(0, ra);
+#pragma unroll 1
+        for (int k = 0; k < rt; k += 2) {
+            const bool has1 = k + 1 < rt;
+            if (has1) load_row(k + 1, rb);
+            compute_row(k, ra);
+            if (k + 2 < rt) load_row(k + 2, ra);
+            if (has1) compute_row(k + 1, rb);
+        }
+        __syncthreads();  // the LDS block is rewritten for the next plane
+    }
     return rmax;
 }
 
@@ -726,6 +1032,8 @@ __device__ __forceinline__ uint64_t run_tile(PDesc& P, PState& S, uint32_t tile,
         } else {
             if constexpr (M == HJR_QUAD_Z2D)
                 return tile_plane<T, 2, HamZ2D<T>, STAGE, RS, ORDER>(P, S, tile, lds);
+            else if constexpr (fam_walk(FAM))
+                return tile_walk<T, HamX4D<T, VD>, STAGE, ORDER>(P, S, tile, lds);
             else
                 return tile_plane<T, 4, HamX4D<T, VD>, STAGE, RS, ORDER>(P, S, tile, lds);
         }

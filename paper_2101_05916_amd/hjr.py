@@ -54,7 +54,7 @@ class Opts(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("order", C.c_int32), ("cfl", C.c_double),
                 ("max_iter", C.c_int64), ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("chunk", C.c_int32), ("flags", C.c_int32),
-                ("tile_rows", C.c_int32), ("reserved", C.c_int32), ("band", C.c_double)]
+                ("tile_rows", C.c_int32), ("walk", C.c_int32), ("band", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -239,7 +239,7 @@ def _dtype_code(dtype) -> int:
 
 
 def make_opts(dtype=None, order=2, cfl=0.8, max_iter=100000, chunk=0, flags=0, stream=None,
-              tile_rows=0, band=0.0) -> Opts:
+              tile_rows=0, band=0.0, walk=0) -> Opts:
     torch = _torch()
     o = Opts()
     lib().hjr_opts_default(C.byref(o))
@@ -250,6 +250,7 @@ def make_opts(dtype=None, order=2, cfl=0.8, max_iter=100000, chunk=0, flags=0, s
     o.chunk = chunk
     o.flags = flags
     o.tile_rows = tile_rows
+    o.walk = walk
     o.band = band
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -329,7 +330,7 @@ def tuned(kind, dtype, n):
 
 def solve(spec: Spec, l, V0=None, V_out=None, *, dtype=None, order=2, cfl=0.8,
           max_iter=100000, chunk=None, flags=0, workspace=True, check=True, tile_rows=None,
-          dfield=None):
+          dfield=None, walk=0):
     """One safe-set solve.  l, V0, V_out: device tensors of spec.size elements.
     dfield: optional per-node disturbance boxes, a device tensor of
     (channels, 2, spec.size) elements (hjr_solve_field); without it the
@@ -350,7 +351,8 @@ def solve(spec: Spec, l, V0=None, V_out=None, *, dtype=None, order=2, cfl=0.8,
     if V_out is None:
         V_out = torch.empty(N, dtype=dtype, device=l.device)
     _check_tensor(V_out, N, dtype, "V_out")
-    o = make_opts(dtype, order, cfl, max_iter, chunk, flags, tile_rows=tile_rows, band=spec.band)
+    o = make_opts(dtype, order, cfl, max_iter, chunk, flags, tile_rows=tile_rows, band=spec.band,
+                  walk=walk)
     ws = None
     if workspace:
         nb = workspace_bytes(spec, o)
@@ -461,7 +463,7 @@ def solve_local(spec: Spec, l, mask, V0=None, V_out=None, *, dtype=None, order=2
 
 
 def solve_levels(spec: Spec, grids_n, ls, V0=None, *, dtype=None, order=2, cfl=0.8,
-                 max_iter=100000, chunk=0, flags=0, masks=False, dfields=None):
+                 max_iter=100000, chunk=0, flags=0, masks=False, dfields=None, walk=0):
     """Coarse-to-fine solve: grids_n is a list of per-level node counts over
     spec's box, ls the per-level constraints, dfields optional per-level
     disturbance fields (hjr_solve_field; no masks then).  Returns (list of V
@@ -482,7 +484,7 @@ def solve_levels(spec: Spec, grids_n, ls, V0=None, *, dtype=None, order=2, cfl=0
         mk = [torch.zeros(int(np.prod([x - 1 for x in n])), dtype=torch.uint8,
                           device=ls[0].device) for n in grids_n]
         mp = (C.c_void_p * nlev)(*[t.data_ptr() for t in mk])
-    o = make_opts(dtype, order, cfl, max_iter, chunk, flags, band=spec.band)
+    o = make_opts(dtype, order, cfl, max_iter, chunk, flags, band=spec.band, walk=walk)
     st = Stats()
     dyn = make_dyn(spec.kind, spec.params)
     if dfields is not None:
@@ -543,7 +545,7 @@ def make_problem(spec: Spec, l, V_out, V0=None, levels=None, tile_rows=None,
 
 
 def solve_batch(problems, *, dtype=None, order=2, cfl=0.8, max_iter=100000, chunk=None,
-                flags=0, device=None):
+                flags=0, device=None, walk=0):
     """problems: list of Problem structs (make_problem).  dtype None takes the
     precision of the problems' arrays (all alike); a dtype that differs from
     it is an error.  chunk None takes the autotuned chunk of the largest grid
@@ -564,7 +566,7 @@ def solve_batch(problems, *, dtype=None, order=2, cfl=0.8, max_iter=100000, chun
         chunk = tuned(big.dyn.kind, dtype or torch.float32,
                       [g.n[i] for i in range(g.ndim)]).get("chunk", 0)
     arr = (Problem * n)(*problems)
-    o = make_opts(dtype or torch.float32, order, cfl, max_iter, chunk, flags)
+    o = make_opts(dtype or torch.float32, order, cfl, max_iter, chunk, flags, walk=walk)
     nb = C.c_size_t(0)
     _raise(lib().hjr_batch_workspace_bytes(n, arr, C.byref(o), C.byref(nb)),
            "hjr_batch_workspace_bytes")
