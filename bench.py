@@ -264,13 +264,14 @@ def mode_mix(args, torch, hjr, W):
         "hbm_frac_end_to_end": value * 24.0 / (HBM_PEAK_GBS * 1e9),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_stage<float,2,X4D narrow, ENO2> (RK stage 2 + projection + residual), "
+            "kernel": "k_stage<float,2,3> (4-D narrow-plane ENO2 family: RK stage 2 + projection + "
+                      "residual), "
                       f"the mix's {n4} 4-D problems batched ({n4nodes} nodes, all live)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic("mix_stage2"),
+            "traffic": measured_traffic("mix_stage2", MIX_TRAFFIC_FILE),
             "bytes_per_cell_update": 16,
             "avg_launch_us": kms[1] / max(kn[1], 1) * 1e3,
             "launches_timed": int(kn[1]),
@@ -413,7 +414,8 @@ def mode_step(args, torch, hjr, W):
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_stage<float,2,X4D narrow, ENO2> (RK stage 2 + projection + residual), "
+            "kernel": "k_stage<float,2,3> (4-D narrow-plane ENO2 family: RK stage 2 + projection + "
+                      "residual), "
                       "x,y 41^4 batched",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -1033,6 +1035,7 @@ def mode_copy(args, torch, hjr, W):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_stage_decomposed_quad10d.json")
+MIX_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_stage_mix256.json")
 KERNEL_SOURCES = ["csrc/hjr_stencil.hpp", "csrc/hjr_kernels.hip", "csrc/hjr_device.hpp",
                   "csrc/hjr_engine.cpp", "tuned.json"]
 
@@ -1049,11 +1052,11 @@ def kernel_hash():
     return h.hexdigest()
 
 
-def measured_traffic(stage_key):
+def measured_traffic(stage_key, path=None):
     """HBM bytes per launch from the committed rocprofv3 counters, or None
     when the kernel sources changed since they were taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path or TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
