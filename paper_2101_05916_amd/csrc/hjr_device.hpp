@@ -39,8 +39,14 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #define HJR_BLOCKS_PER_CU_F64 14     // the same for the FP64 kernels (15, which their LDS
                                      // allows, measured 17-20 % slower)
 #endif
-#ifndef HJR_I0_BLOCK
-#define HJR_I0_BLOCK 4               // 4-D plane tiles: axis-0 indices per block of the plane order
+#ifndef HJR_PLANE_BLOCK
+#define HJR_PLANE_BLOCK 4            // 4-D plane tiles: axis-0 indices per block of the plane order
+#endif
+#ifndef HJR_TILES_PER_WG_MAX
+#define HJR_TILES_PER_WG_MAX 16      // more tiles per workgroup of the capped grid: a workgroup per
+#endif                               // run of HJR_TILES_PER_RUN tiles (0: always the capped grid)
+#ifndef HJR_TILES_PER_RUN
+#define HJR_TILES_PER_RUN 8
 #endif
 #ifndef HJR_STAGE_DMA
 #define HJR_STAGE_DMA 3              // plane tiles staged by direct global-to-LDS loads: bit 0
@@ -268,6 +274,7 @@ struct ChunkHdr {
     int32_t pad;
     int64_t fam_tile[kNumFam + 1];
     int32_t fam_pos[kNumFam + 1];
+    int32_t fam_run[2][kNumFam];  // per stage and family: consecutive tiles a workgroup takes at a time
 };
 constexpr int kHdrBytes = 512;  // device slot of the chunk header, before the ProbCtl array
 static_assert(sizeof(ChunkHdr) <= kHdrBytes, "ChunkHdr must fit its slot");

@@ -453,8 +453,9 @@ void Engine::fill_desc(const Job* j, ProbDesc& P, int walk) const
             int64_t outer = 1;
             for (int a = 0; a < D - 2; a++) outer *= g.n[a];
             P.ntiles = outer * chunks;
-            if (D == 4 && !walks && HJR_I0_BLOCK > 1 && g.n[0] > 1) {
-                const int bx = std::min<int>(HJR_I0_BLOCK, g.n[0]);
+            // planes in blocks of bx consecutive axis-0 indices
+            if (D == 4 && !walks && HJR_PLANE_BLOCK > 1 && g.n[0] > 1) {
+                const int bx = std::min<int>(HJR_PLANE_BLOCK, g.n[0]);
                 P.bx = bx;
                 P.nblk = (g.n[0] + bx - 1) / bx;
                 P.bxl = g.n[0] - (P.nblk - 1) * bx;
@@ -675,6 +676,8 @@ hjr_status Engine::step()
         hdr->fam_tile[f] = fam_tile_[f];
         hdr->fam_pos[f] = fam_pos_[f];
     }
+    for (int st = 0; st < 2; st++)
+        for (int f = 0; f < kNumFam; f++) hdr->fam_run[st][f] = 1;
     for (int s = 0; s < cap; s++) {
         Job* j = slots_[s];
         ctl[s].limit = 0;
@@ -700,7 +703,6 @@ hjr_status Engine::step()
         flights_.erase(flights_.begin());
         return process(g);
     }
-    HJR_TRY(hipMemcpyAsync(d_hdr_[par], h_ctl_[par], ctl_bytes_, hipMemcpyHostToDevice, stream_));
     // one launch per family present, with no more workgroups than it has
     // tiles (a multiple of 8, so that every XCD gets its share)
     launches_.clear();
@@ -714,11 +716,29 @@ hjr_status Engine::step()
         const int64_t set_bytes = fam_nodes_[fm] * 3 * (cfg_.dtype == HJR_F64 ? 8 : 4);
         const bool capped = set_bytes > HJR_BIG_SET_BYTES || nfam > 1;
         for (int st = 0; st < 2; st++) {
-            const int cap = st == 1 && capped ? fam_grid_big_[fm] : fam_grid_[st][fm];
+            int cap = st == 1 && capped ? fam_grid_big_[fm] : fam_grid_[st][fm];
+            // A capped grid strides through the tiles; over many tiles per
+            // workgroup its workgroups drift apart, the tiles in flight on an
+            // XCD no longer lie together, and the neighbour planes they read
+            // miss L2 (the 121 4-D problems of the 256-problem mix: 4.6x the
+            // algorithmic reads in stage 1).  There every tile gets its own
+            // workgroup: the dispatcher starts them in order, so the tiles in
+            // flight stay a compact window (1.7x).
+            // (Workgroups take runs of HJR_TILES_PER_RUN consecutive tiles,
+            // so that the per-workgroup setup -- problem lookup, convergence
+            // vote, residual flush -- is shared by several tiles.)
+            int run = 1;
+            if (cfg_.grid <= 0 && HJR_TILES_PER_WG_MAX > 0 && nt > (int64_t)cap * HJR_TILES_PER_WG_MAX) {
+                run = HJR_TILES_PER_RUN;
+                const int64_t per_xcd = (nt + 7) / 8;
+                cap = (int)std::min<int64_t>(INT32_MAX / 16, (per_xcd + run - 1) / run) * 8;
+            }
+            hdr->fam_run[st][fm] = run;
             l.grid[st] = (int)std::min<int64_t>(cap, std::max<int64_t>(8, (nt + 7) / 8 * 8));
         }
         launches_.push_back(l);
     }
+    HJR_TRY(hipMemcpyAsync(d_hdr_[par], h_ctl_[par], ctl_bytes_, hipMemcpyHostToDevice, stream_));
     if (use_graph_) {
         hipGraphExec_t ge = nullptr;
         for (auto& g : graphs_[par])

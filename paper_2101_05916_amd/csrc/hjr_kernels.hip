@@ -7,11 +7,15 @@
 // grid; it is a memory-bound cross-shaped stencil (9 points in 2-D, 17 in
 // 4-D), so it runs on the vector ALUs with coalesced loads, not on MFMA.
 //
-// Work decomposition: every problem of a batch is cut into tiles of kTile
-// consecutive nodes; the tiles of all problems form one index space that a
-// fixed-size grid of workgroups strides through.  Workgroup b runs on XCD
-// b mod 8, and each XCD takes one contiguous eighth of the tile space, so
-// the planes a tile's stencil touches are mostly in that XCD's L2.
+// Work decomposition: every problem of a batch is cut into tiles (plane
+// tiles: a few rows of the plane of the two fastest axes; flat tiles: kTile
+// consecutive nodes); the tiles of all problems form one index space.
+// Workgroup b runs on XCD b mod 8, and each XCD takes one contiguous eighth
+// of the tile space, so the planes a tile's stencil touches are mostly in
+// that XCD's L2.  A grid capped at a few workgroups per CU strides through
+// the tiles; when that would be many tiles per workgroup the host launches
+// one workgroup per tile instead, which keeps the tiles in flight on an XCD
+// together (a striding grid drifts apart over a long run).
 //
 // Convergence is decided on the device: stage 2 max-reduces |V' - V| per
 // workgroup (wave shuffles, then LDS) and folds it into the problem's
@@ -127,7 +131,8 @@ __device__ __forceinline__ void flush_residual(const ChunkArgs& A, int p, uint64
 
 // One RK stage over the tiles of family FAM.  The family's tiles are split
 // into eight contiguous ranges, one per XCD (workgroup b runs on XCD b mod
-// 8), and the workgroups of an XCD stride through its range.
+// 8), and the workgroups of an XCD stride through its range (one tile each
+// when the grid has a workgroup per tile).
 template <typename T, int STAGE, int FAM>
 __global__ __launch_bounds__(kStageBlock) HJR_STAGE_ATTR void k_stage(ChunkArgs A)
 {
@@ -150,23 +155,27 @@ __global__ __launch_bounds__(kStageBlock) HJR_STAGE_ATTR void k_stage(ChunkArgs 
     const int xcd = (int)blockIdx.x & 7;
     const int local = (int)blockIdx.x >> 3;
     const int64_t beg = t0 + total * xcd / 8, end = t0 + total * (xcd + 1) / 8;
+    const int run = hdr->fam_run[STAGE - 1][FAM];  // consecutive tiles per turn (>= 1)
     int cur = -1;
     int64_t lo = 0, hi = 0;  // tile range of the current problem
     bool active = false;
     uint64_t rmax = 0, seen = 0;
-    for (int64_t t = beg + local; t < end; t += G8) {
-        if (t >= hi || t < lo) {
-            const int pos = find_pos(tb, pb, pe, t);
-            if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red, seen);
-            cur = ord[pos];
-            lo = tb[pos];
-            hi = pos + 1 < pe ? tb[pos + 1] : t1;
-            rmax = 0;
-            active = prob_active(A, cur);
-            if (STAGE == 2 && active) seen = __atomic_load_n(residual_word(A, cur), __ATOMIC_RELAXED);
+    for (int64_t r0 = beg + (int64_t)local * run; r0 < end; r0 += (int64_t)G8 * run) {
+        const int64_t r1 = r0 + run < end ? r0 + run : end;
+        for (int64_t t = r0; t < r1; t++) {
+            if (t >= hi || t < lo) {
+                const int pos = find_pos(tb, pb, pe, t);
+                if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red, seen);
+                cur = ord[pos];
+                lo = tb[pos];
+                hi = pos + 1 < pe ? tb[pos + 1] : t1;
+                rmax = 0;
+                active = prob_active(A, cur);
+                if (STAGE == 2 && active) seen = __atomic_load_n(residual_word(A, cur), __ATOMIC_RELAXED);
+            }
+            if (!active) continue;
+            rmax = umax64(rmax, run_tile<T, STAGE, FAM>(probs[cur], states[cur], (uint32_t)(t - lo), lds));
         }
-        if (!active) continue;
-        rmax = umax64(rmax, run_tile<T, STAGE, FAM>(probs[cur], states[cur], (uint32_t)(t - lo), lds));
     }
     if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red, seen);
 }

@@ -622,10 +622,11 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
     int i0 = 0, i1 = 0;
     if (D == 4) {
         if (P.bx > 1) {
-            // blocked order: blocks of bx consecutive axis-0 indices, axis 1
-            // next, axis 0 fastest inside a block (the last block may be
-            // shorter); workgroups running together then hold a compact
-            // patch of (i0, i1) planes, whose neighbour planes stay in L2
+            // blocked order: blocks of bx consecutive axis-0 indices (the
+            // last block may be shorter), axis 1 next, axis 0 fastest inside
+            // a block; workgroups running together then hold a compact patch
+            // of (i0, i1) planes, and the neighbour planes they read were
+            // staged recently
             const uint32_t blk = fdiv(outer, P.div_bxn1);
             const int rem = (int)(outer - blk * (uint32_t)(P.bx * P.n[1]));
             int q, bxs;
@@ -722,60 +723,76 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
     uint64_t rmax = 0;
     constexpr int kUnroll = STAGE == 1 ? kNodeUnroll1 : kNodeUnroll2;
     static_assert(kPlaneNodesPT * kStageBlock * kRowStrideL < (1 << 20), "fdiv20 range");
+    // a lane's node k (e = lane + 64 k; lanes past the end take the tile's
+    // last node again and drop the result): its place in the tile and its
+    // global operands
+    struct NodeIn {
+        uint32_t vb;  // byte offset of the node
+        int rr, cc;   // its row and column in the tile
+        T w[8];       // outer-axis samples (D = 4)
+        typename Ham::Node nd;
+        T vo, lv;     // stage 2: V and l at the node
+    };
+    auto load_node = [&](int k, NodeIn& N) {
+        const int e = min(tid + k * kStageBlock, cnt - 1);
+        N.vb = (node0 + (uint32_t)e) * B;
+        N.rr = (int)fdiv20((uint32_t)e, P.div_last);
+        N.cc = e - (int)__umul24((uint32_t)N.rr, (uint32_t)nc);
+        if (D == 4) {
+#pragma unroll
+            for (int qq = 0; qq < 8; qq++) N.w[qq] = gld1<T>(nb[qq], N.vb);
+        }
+        // per-node Hamiltonian data (row coefficient, disturbance box)
+        N.nd = ham.node_b(r0 + N.rr, N.vb);
+        N.vo = N.lv = T(0);
+        if (STAGE == 2) {
+            N.vo = gld1<T>(vout, N.vb);
+            N.lv = gld1<T>(lc, N.vb);
+        }
+    };
+    auto compute_node = [&](int k, const NodeIn& N) {
+        const bool live = tid + k * kStageBlock < cnt;
+        const int rr = N.rr, cc = N.cc;
+        const T* q = lds + __umul24((uint32_t)rr, (uint32_t)RS) + cc + (2 * RS + 2);
+        const T c = q[0];
+        T sum[4], dif;
+        eno_sd<T, ORDER>(q[-2 * RS], q[-RS], c, q[RS], q[2 * RS], sum[ra], dif);
+        T L = ah[ra] * dif;
+        eno_sd<T, ORDER>(q[-2], q[-1], c, q[1], q[2], sum[ca], dif);
+        L += ah[ca] * dif;
+        if (D == 4) {
+            T m2 = N.w[0], m1 = N.w[1], p1 = N.w[2], p2 = N.w[3];
+            if (edge0) ghost_fix<T>(i0, P.n[0], c, m2, m1, p1, p2);
+            eno_sd<T, ORDER>(m2, m1, c, p1, p2, sum[0], dif);
+            L += ah[0] * dif;
+            m2 = N.w[4];
+            m1 = N.w[5];
+            p1 = N.w[6];
+            p2 = N.w[7];
+            if (edge1) ghost_fix<T>(i1, P.n[1], c, m2, m1, p1, p2);
+            eno_sd<T, ORDER>(m2, m1, c, p1, p2, sum[1], dif);
+            L += ah[1] * dif;
+            L += ham.eval(sum, i0, i1, r0 + rr, cc, N.nd);
+        } else {
+            L += ham.eval(sum, r0 + rr, cc, 0, 0, N.nd);
+        }
+        if (STAGE == 1) {
+            if (live) gst1<T>(c + dt * L, vout, N.vb);
+        } else {
+            const T vt = c + dt * L;
+            const T avg = T(0.5) * (N.vo + vt);
+            const T vn = (N.lv < avg) ? N.lv : avg;
+            if (live) gst1<T>(vn, vout, N.vb);
+            const uint64_t r = dbits(fabs((double)vn - (double)N.vo));
+            if (live && in_band(vn, N.vo, P)) rmax = umax64(rmax, r);
+        }
+    };
 #pragma unroll kUnroll
     for (int k = 0; k < kPlaneNodesPT; k++) {
         if (k * kStageBlock < cnt) {
-            // lanes past the end compute the last node again and drop it
-            const int e = min(tid + k * kStageBlock, cnt - 1);
-            const bool live = tid + k * kStageBlock < cnt;
-            const uint32_t vb = (node0 + (uint32_t)e) * B;
-            const int rr = (int)fdiv20((uint32_t)e, P.div_last);
-            const int cc = e - (int)__umul24((uint32_t)rr, (uint32_t)nc);
-            T w[8];
-            if (D == 4) {
-#pragma unroll
-                for (int qq = 0; qq < 8; qq++) w[qq] = gld1<T>(nb[qq], vb);
-            }
-            // per-node Hamiltonian data (row coefficient, disturbance box)
-            const typename Ham::Node nd = ham.node_b(r0 + rr, vb);
-            T vo = T(0), lvv = T(0);
-            if (STAGE == 2) {
-                vo = gld1<T>(vout, vb);
-                lvv = gld1<T>(lc, vb);
-            }
-            const T* q = lds + __umul24((uint32_t)rr, (uint32_t)RS) + cc + (2 * RS + 2);
-            const T c = q[0];
-            T sum[4], dif;
-            eno_sd<T, ORDER>(q[-2 * RS], q[-RS], c, q[RS], q[2 * RS], sum[ra], dif);
-            T L = ah[ra] * dif;
-            eno_sd<T, ORDER>(q[-2], q[-1], c, q[1], q[2], sum[ca], dif);
-            L += ah[ca] * dif;
-            if (D == 4) {
-                T m2 = w[0], m1 = w[1], p1 = w[2], p2 = w[3];
-                if (edge0) ghost_fix<T>(i0, P.n[0], c, m2, m1, p1, p2);
-                eno_sd<T, ORDER>(m2, m1, c, p1, p2, sum[0], dif);
-                L += ah[0] * dif;
-                m2 = w[4];
-                m1 = w[5];
-                p1 = w[6];
-                p2 = w[7];
-                if (edge1) ghost_fix<T>(i1, P.n[1], c, m2, m1, p1, p2);
-                eno_sd<T, ORDER>(m2, m1, c, p1, p2, sum[1], dif);
-                L += ah[1] * dif;
-                L += ham.eval(sum, i0, i1, r0 + rr, cc, nd);
-            } else {
-                L += ham.eval(sum, r0 + rr, cc, 0, 0, nd);
-            }
-            if (STAGE == 1) {
-                if (live) gst1<T>(c + dt * L, vout, vb);
-            } else {
-                const T vt = c + dt * L;
-                const T avg = T(0.5) * (vo + vt);
-                const T vn = (lvv < avg) ? lvv : avg;
-                if (live) gst1<T>(vn, vout, vb);
-                const uint64_t r = dbits(fabs((double)vn - (double)vo));
-                if (live && in_band(vn, vo, P)) rmax = umax64(rmax, r);
-            }
+            NodeIn N;
+            load_node(k, N);
+            compute_node(k, N);
         }
     }
     __syncthreads();  // the LDS block is reused by the next tile

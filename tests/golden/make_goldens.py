@@ -1,5 +1,5 @@
-"""Write the stored oracle results of converged 4-D x-subsystem solves that the
-GPU parity tests compare against (tests/golden/x4d_*.npz).
+"""Write the stored oracle results of converged solves that the GPU parity
+tests and bench.py's precision mode compare against (tests/golden/*.npz).
 
 Calls only the FP64 oracle (oracle/) and the seeded input generators
 (paper_2101_05916_amd/workloads.py, which hold no solver arithmetic).
@@ -20,6 +20,11 @@ carry the value to a finer one by multilinear interpolation, continue):
                  solve there, then -> 41^4 -> 61^4.
   mix5_31_band   problem 5 of the seeded 256-problem mix: 31^4, bound
                  0.7837..., residual band 0.5, cold.
+  z2d_101_d05    the 2-D vertical quadcopter on 101^2, bound 0.5, cold,
+                 stop over every node.
+  z2d_chain_d05  51^2 cold -> 101^2, bound 0.5: the z-subsystem of the
+                 decomposed near-hover quadcopter's initial safe set.
+  z2d_mix0       the first 2-D problem of the seeded 256-problem mix, cold.
 
 Per level the file holds the oracle's step count, dt, alpha and its last
 eight residuals, the packed signs (V >= 0) of the FP64 value at every node,
@@ -28,7 +33,7 @@ for |V| <= 4), either at every node or, for the 41^4 and 61^4 levels of the
 61^4 chains, at 2^18 nodes drawn with numpy default_rng(20210115) (their
 flat indices are stored too).
 
-Run from the repository root:  python tests/golden/make_x4d_goldens.py
+Run from the repository root:  python tests/golden/make_goldens.py [case ...]
 (about 40 minutes of single-threaded oracle time per 61^4 chain; the cases
 run in parallel processes).
 """
@@ -141,6 +146,18 @@ def case_mix5():
     return pack(chain([P]), [P], [False])
 
 
+def case_z2d():
+    P = W.quad_z2d(101, 0.5, "z")
+    a = pack(chain([P]), [P], [False])
+    Ps = [W.quad_z2d(n, 0.5, "z") for n in (51, 101)]
+    b = pack(chain(Ps), Ps, [False, False])
+    man = W.batch_manifest(256, seed=0)
+    e = next(e for e in man if e["kind"] == W.QUAD_Z2D)
+    Q = W.problem_from_manifest(e)
+    c = pack(chain([Q]), [Q], [False], extra={"mix_index": np.array([e["index"]])})
+    return a, b, c
+
+
 def _run(name):
     t0 = time.perf_counter()
     print(f"{name}: start", flush=True)
@@ -151,6 +168,9 @@ def _run(name):
         res = {"x4d_c2f_d05_band": a, "x4d_upd_d08_band": b}
     elif name == "mix5":
         res = {"x4d_mix5_31_band": case_mix5()}
+    elif name == "z2d":
+        a, b, c = case_z2d()
+        res = {"z2d_101_d05": a, "z2d_chain_d05": b, "z2d_mix0": c}
     else:
         raise ValueError(name)
     for fname, d in res.items():
@@ -160,6 +180,6 @@ def _run(name):
 
 
 if __name__ == "__main__":
-    names = sys.argv[1:] or ["c2f", "chain_d05", "mix5"]
+    names = sys.argv[1:] or ["c2f", "chain_d05", "mix5", "z2d"]
     with Pool(len(names)) as pool:
         pool.map(_run, names)

@@ -256,7 +256,12 @@ REQS = [(0, 0.5), (1, 0.5), (2, 0.5), (0, 0.8), (3, 0.4), (1, 0.3), (2, 0.7), (0
 @pytest.mark.parametrize("mode", ["alone", "mix"])
 def test_server_matches_sequential_solves(mode):
     """Each result equals the single-solve reference whether the requests
-    run one at a time or all overlap on the device (continuous batching)."""
+    run one at a time or all overlap on the device (continuous batching).
+    One at a time, every reply's value (the instance's resident value right
+    after it) is compared with the reference bit for bit; overlapped, a later
+    request of an instance may already have replaced it, so the values are
+    compared at the end, and an intermediate value is checked through the
+    step count and result of the request warm-started from it."""
     hjr = hjr_()
     specs, ls = make_instances()
     ref, last = server_reference(REQS, specs, ls)
@@ -269,7 +274,11 @@ def test_server_matches_sequential_solves(mode):
             seen.add(inst)
             t = srv.submit(inst, spec, lh)
             if mode == "alone":
-                replies.append(srv.wait(t))
+                rep = srv.wait(t)
+                replies.append(rep)
+                rv = ref[len(replies) - 1][0]
+                assert rep["status"] == hjr.OK
+                assert np.array_equal(srv.read_value(inst, specs[inst].size), rv)
             else:
                 tickets.append(t)
         if mode == "mix":
@@ -309,8 +318,20 @@ def test_server_small_budget_queues_and_evicts():
         used, _ = srv.memory()
         assert used <= budget
         V1, st1 = hjr.solve(hjr.Spec.of(specs[0]), ls[0])
+        torch.cuda.synchronize()
         for rep in reps:
             assert rep["status"] == hjr.OK and rep["iterations"] == st1["iterations"]
+        # every instance still resident holds exactly the single solve's value
+        resident = 0
+        for k in range(3):
+            try:
+                got = srv.read_value(k, N)
+            except hjr.HjrError as e:
+                assert e.status == hjr.ENOTFOUND
+                continue  # evicted to make room for a later instance
+            resident += 1
+            assert np.array_equal(got, V1.cpu().numpy())
+        assert resident >= 1
 
 
 def test_server_not_converged_keeps_resident_value():

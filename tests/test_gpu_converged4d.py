@@ -1,5 +1,5 @@
 """Converged 4-D x-subsystem solves on the device against the oracle's stored
-results (tests/golden/x4d_*.npz, written by tests/golden/make_x4d_goldens.py,
+results (tests/golden/x4d_*.npz, written by tests/golden/make_goldens.py,
 which calls only the oracle): the initial safe set of the decomposed
 near-hover quadcopter (21^4 -> 41^4), the initial safe set and the bound
 update 0.5 -> 0.8 of the warm-start / coarse-to-fine study (21^4 -> 41^4 ->
