@@ -68,6 +68,8 @@ def parse():
                     help="mix mode: RK2 steps of the profiled 4-D pass")
     ap.add_argument("--copy-mib", type=int, default=2048, help="copy mode: MiB per copy")
     ap.add_argument("--chunk", type=int, default=None, help="RK2 steps per chunk (default: autotuned)")
+    ap.add_argument("--local-n", type=int, default=41, help="local mode: nodes per axis of the 4-D grid")
+    ap.add_argument("--local-dbar", type=float, default=0.55, help="local mode: the updated bound")
     ap.add_argument("--walk", type=int, default=0,
                     help="4-D narrow-plane problems: axis-0 planes per walking workgroup "
                          "(0 or -1 = plane tiles, the default)")
@@ -770,13 +772,15 @@ def mode_quad10d(args, torch, hjr, W):
 # ---------------------------------------------------------------------------
 
 def mode_local(args, torch, hjr, W):
-    """x-subsystem 41^4, FP32, residual band 0.5: converge for the bound
-    0.5, then update to 0.55 warm-started from it, (a) over the whole grid,
-    (b) over the band of k = 2 and k = 4 cells around the previous zero
-    level set only (hjr_solve_local); zero-level disagreement of (b)
-    against (a)."""
-    P5 = W.quad_x4d(41, 0.5, band=W.BAND_4D_UPDATE)
-    P55 = W.quad_x4d(41, 0.55, band=W.BAND_4D_UPDATE)
+    """x-subsystem on --local-n^4 (41 by default), FP32, residual band 0.5:
+    converge for the bound 0.5, then update to --local-dbar (0.55) warm-started from it,
+    (a) over the whole grid, (b) over the band of k = 2 and k = 4 cells
+    around the previous zero level set only (hjr_solve_local: masked plane
+    tiles, tiles without a band node skipped); zero-level disagreement of
+    (b) against (a)."""
+    n, dbar = args.local_n, args.local_dbar
+    P5 = W.quad_x4d(n, 0.5, band=W.BAND_4D_UPDATE)
+    P55 = W.quad_x4d(n, dbar, band=W.BAND_4D_UPDATE)
     spec = hjr.Spec.of(P55)
     l = torch.tensor(P5.l, dtype=torch.float32, device="cuda")
     old, _ = hjr.solve(hjr.Spec.of(P5), l)
@@ -795,8 +799,8 @@ def mode_local(args, torch, hjr, W):
 
     Vfull, full = run(lambda: hjr.solve(spec, l, V0=old))
     progress(f"local mode full: {full['ms_p50']:.1f} ms, {full['iterations']} steps")
-    out = {"mode": "local", "workload": "x-subsystem 41^4, FP32, warm update of the bound "
-           "0.5 -> 0.55", "full": full}
+    out = {"mode": "local", "workload": f"x-subsystem {n}^4, FP32, warm update of the bound "
+           f"0.5 -> {dbar}", "full": full}
     for k in (2, 4):
         mask, cnt = hjr.band_mask(spec, old, k)
         Vb, row = run(lambda: hjr.solve_local(spec, l, mask, V0=old))

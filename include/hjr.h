@@ -300,7 +300,10 @@ hjr_status hjr_band_mask(const hjr_grid* g, const void* V, int32_t k, uint8_t* n
  * node_mask[i] != 0 (DEVICE, N bytes) are updated; every other node keeps
  * its initial value min(l, V0) throughout and serves as boundary data, and
  * the residual runs over the masked nodes (an empty mask stops after one
- * step).  Runs on the flat tiles and skips tiles without a masked node.
+ * step).  The 4-D x-subsystem with ENO2 and constant boxes runs on plane
+ * tiles, over the list of the tiles that hold a masked node (built once per
+ * solve, with a device-to-host copy of one flag per tile); every other case
+ * runs on the flat tiles and skips tiles without a masked node.
  * stats->cell_updates counts masked nodes x steps.  Synchronises o->stream. */
 hjr_status hjr_solve_local(const hjr_dyn* dyn, const hjr_grid* grid, const void* l, const void* V0,
                            const hjr_dstb* d, const void* dfield, const uint8_t* node_mask,

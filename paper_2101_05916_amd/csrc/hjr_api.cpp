@@ -77,8 +77,23 @@ bool same_box(const hjr_grid& a, const hjr_grid& b)
     return true;
 }
 
+// Per-tile scratch of a localized update (level 0): a flag per tile -- flat
+// tiles (N / kTile of them) or plane tiles of at least one row (at most
+// N / n_last of them) -- and the list of the live plane tiles (4 bytes each).
+static int64_t mask_flag_bytes(const hjr_grid& g)
+{
+    const int64_t N = grid_size(g);
+    return align256(std::max<int64_t>(N / kTile, N / g.n[g.ndim - 1]) + 1);
+}
+
+static int64_t mask_tile_bytes(const hjr_grid& g)
+{
+    const int64_t N = grid_size(g);
+    return mask_flag_bytes(g) + align256(4 * (N / g.n[g.ndim - 1] + 1));
+}
+
 // Scratch of one job: the stage-1 array, the lookup table and the per-tile
-// flags of a localized update.
+// flags and list of a localized update.
 size_t job_scratch_bytes(const hjr_grid* grids, int nlev, int dtype)
 {
     int64_t N = 0, n2 = 0;
@@ -86,9 +101,8 @@ size_t job_scratch_bytes(const hjr_grid* grids, int nlev, int dtype)
         N = std::max<int64_t>(N, grid_size(grids[k]));
         if (grids[k].ndim >= 3) n2 = std::max<int64_t>(n2, grids[k].n[2]);
     }
-    // (a localized update runs on flat tiles: N / kTile of them)
     return align256(N * elem_size(dtype)) + align256(std::max<int64_t>(n2, 1) * elem_size(dtype)) +
-           align256(N / kTile + 1);
+           mask_tile_bytes(grids[0]);
 }
 
 // Idle engines are kept for reuse, keyed by what fixes their device tables,
@@ -335,6 +349,7 @@ hjr_status solve_levels_impl(const hjr_dyn* dyn, int32_t nlev, const hjr_grid* g
         if (umask) {
             j.lev[0].umask = umask;
             j.lev[0].tmask = (uint8_t*)((char*)j.table + align256(n2 * elem_size(op.dtype)));
+            j.lev[0].tlist = (uint32_t*)((char*)j.lev[0].tmask + mask_flag_bytes(grids[0]));
             if ((st = eng.count_mask(umask, grid_size(grids[0]), &updated)) != HJR_OK) return st;
         }
         if ((st = eng.add(&j)) != HJR_OK) return st;

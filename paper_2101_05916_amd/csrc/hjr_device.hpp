@@ -48,6 +48,9 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #ifndef HJR_TILES_PER_RUN
 #define HJR_TILES_PER_RUN 8
 #endif
+#ifndef HJR_RES_FILTER
+#define HJR_RES_FILTER 1             // FP32 stage 2: exact residual only where the float one can raise the max
+#endif
 #ifndef HJR_STAGE_DMA
 #define HJR_STAGE_DMA 3              // plane tiles staged by direct global-to-LDS loads: bit 0
 #endif                               // stage 1, bit 1 stage 2 (else through registers)
@@ -101,8 +104,14 @@ enum Family : int32_t {
     kFamZ2dS2F, kFamZ2dL2F, kFamX4dS2F, kFamX4dL2F,
     kFamXvS2, kFamXvL2, kFamXvS2F, kFamXvL2F,  // QUAD_X4DV
     kFamX4dW2, kFamX4dW1, kFamXvW2,            // walking tiles (narrow planes)
+    kFamX4dMS2, kFamX4dML2,                    // localized updates (node mask), narrow / wide
     kNumFam
 };
+
+__host__ __device__ constexpr bool fam_masked(int f)
+{
+    return f == kFamX4dMS2 || f == kFamX4dML2;
+}
 
 __host__ __device__ constexpr bool fam_walk(int f)
 {
@@ -113,7 +122,7 @@ __host__ __device__ constexpr bool fam_walk(int f)
 __host__ __device__ constexpr int fam_model(int f)
 {
     return f == kFamFlat ? -1
-         : f == kFamX4dW2 || f == kFamX4dW1 ? HJR_QUAD_X4D
+         : f == kFamX4dW2 || f == kFamX4dW1 || fam_masked(f) ? HJR_QUAD_X4D
          : f == kFamXvW2 ? HJR_QUAD_X4DV
          : f >= kFamXvS2 ? HJR_QUAD_X4DV
          : (((f - 1) & 3) >= 2 ? HJR_QUAD_X4D : HJR_QUAD_Z2D);
@@ -123,7 +132,10 @@ __host__ __device__ constexpr int fam_model(int f)
 // (Z2D S, Z2D L, X4D S, X4D L) and in the QUAD_X4DV group (S, L, S, L).
 __host__ __device__ constexpr int fam_rs(int f)
 {
-    return f == kFamFlat ? 0 : f >= kFamX4dW2 ? kRowStrideS : (((f - 1) & 1) ? kRowStrideL : kRowStrideS);
+    return f == kFamFlat ? 0
+         : f == kFamX4dML2 ? kRowStrideL
+         : f >= kFamX4dW2 ? kRowStrideS
+         : (((f - 1) & 1) ? kRowStrideL : kRowStrideS);
 }
 
 __host__ __device__ constexpr int fam_order(int f)
@@ -203,6 +215,8 @@ struct ProbDesc {
     const void* dfield;      // per-node disturbance boxes (channel, lower/upper, node), or null
     const uint8_t* umask;    // localized update: nodes to update (others keep their value), or null
     const uint8_t* tmask;    // with umask: per flat tile, whether it holds a node to update
+    const uint32_t* tlist;   // with umask on plane tiles: the tiles holding a node to update
+                             // (ntiles of them), in tile order
     int64_t tile_begin;      // first global tile of this problem
     int64_t ntiles;
     // walking plane tiles (4-D narrow planes, last axis <= 64 nodes): a
@@ -242,6 +256,7 @@ inline int family_of(const ProbDesc& P)
     if (P.path == kPathWalk)
         return P.kind == HJR_QUAD_X4DV ? kFamXvW2 : (P.order == 1 ? kFamX4dW1 : kFamX4dW2);
     const bool narrow = P.path == kPathPlaneS;
+    if (P.umask) return narrow ? kFamX4dMS2 : kFamX4dML2;  // 4-D model, ENO2, no field
     if (P.kind == HJR_QUAD_X4DV) return (P.dfield ? kFamXvS2F : kFamXvS2) + (narrow ? 0 : 1);
     const bool x4 = P.kind == HJR_QUAD_X4D;
     // first of the group Z2D S, Z2D L, X4D S, X4D L

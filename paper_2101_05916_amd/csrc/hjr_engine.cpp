@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "hjr_launch.hpp"
 
@@ -372,6 +373,7 @@ void Engine::fill_desc(const Job* j, ProbDesc& P, int walk) const
     P.dfield = L.dfield;
     P.umask = L.umask;
     P.tmask = L.tmask;
+    P.tlist = L.tlist;
     const int D = g.ndim;
     for (int a = 0; a < D; a++) {
         P.hih[a] = 0.5 / P.h[a];
@@ -416,11 +418,14 @@ void Engine::fill_desc(const Job* j, ProbDesc& P, int walk) const
     P.path = kPathFlat;
     P.ntiles = (P.N + kTile - 1) / kTile;
     // (per-node disturbance boxes and QUAD_X4DV have plane families for ENO2
-    // only; localized updates run on flat tiles)
+    // only; localized updates have masked plane families for the 4-D
+    // x-subsystem with ENO2 and constant bounds, and run on flat tiles
+    // otherwise)
     const bool plane_kind =
         (P.kind == HJR_QUAD_Z2D || P.kind == HJR_QUAD_X4D || P.kind == HJR_QUAD_X4DV) &&
-        !(cfg_.flags & HJR_FLAG_FLAT_TILES) && !P.umask &&
-        !((P.dfield || P.kind == HJR_QUAD_X4DV) && P.order != 2);
+        !(cfg_.flags & HJR_FLAG_FLAT_TILES) &&
+        !((P.dfield || P.kind == HJR_QUAD_X4DV) && P.order != 2) &&
+        !(P.umask && (P.kind != HJR_QUAD_X4D || D != 4 || P.order != 2 || P.dfield));
     // plane tiles address with 32-bit byte offsets
     const bool fits32 = (double)P.N * (double)elem_size(cfg_.dtype) < 4294967296.0;
     if (plane_kind && fits32 && (D == 2 || D == 4)) {
@@ -437,7 +442,7 @@ void Engine::fill_desc(const Job* j, ProbDesc& P, int walk) const
             // walking tiles: 4-D models without per-node bounds on narrow
             // planes of at most kWalkMaxCols columns
             const bool walks = walk > 0 && D == 4 && rs == kRowStrideS && nc <= kWalkMaxCols &&
-                               !P.dfield && P.kind != HJR_DI2X2;
+                               !P.dfield && !P.umask && P.kind != HJR_DI2X2;
             // rows per tile: at most kPlaneNodesPT nodes per thread, and the
             // LDS block within plane_elems
             int want = std::min(plane_elems(rs) / rs - 4, kPlaneNodesPT * kStageBlock / nc);
@@ -475,12 +480,16 @@ void Engine::fill_desc(const Job* j, ProbDesc& P, int walk) const
                 P.ntiles = (int64_t)P.ngroups * chunks * P.nseg;
                 P.path = kPathWalk;
             }
+            // a localized update on plane tiles runs over the list of its
+            // live tiles once the level setup has built it
+            if (P.umask && L.live_tiles >= 0) P.ntiles = L.live_tiles;
         }
     }
 }
 
 hjr_status Engine::setup_level(Job* j)
 {
+    j->lev[j->cur].live_tiles = -1;
     const Level& L = j->lev[j->cur];
     ProbDesc P;
     fill_desc(j, P);
@@ -494,7 +503,26 @@ hjr_status Engine::setup_level(Job* j)
     if (L.umask) {
         // nodes outside the mask keep V, so stage 2 reads Vhat = V there
         HJR_TRY(launch_copy(stream_, cfg_.dtype, L.V, j->Vhat, P.N));
-        HJR_TRY(launch_tile_flags(stream_, L.umask, P.N, kTile, L.tmask, nullptr));
+        if (P.path == kPathFlat) {
+            HJR_TRY(launch_tile_flags(stream_, L.umask, P.N, kTile, L.tmask, nullptr));
+        } else {
+            // flags per plane tile, then the list of the live ones (built on
+            // the host: once per level, a few hundred KB at 61^4)
+            HJR_TRY(launch_plane_tile_flags(stream_, P, L.umask, L.tmask));
+            std::vector<uint8_t> flags((size_t)P.ntiles);
+            HJR_TRY(hipMemcpyAsync(flags.data(), L.tmask, flags.size(), hipMemcpyDeviceToHost, stream_));
+            HJR_TRY(hipStreamSynchronize(stream_));
+            std::vector<uint32_t> list;
+            list.reserve(flags.size());
+            for (size_t t = 0; t < flags.size(); t++)
+                if (flags[t]) list.push_back((uint32_t)t);
+            if (!list.empty()) {
+                HJR_TRY(hipMemcpyAsync(L.tlist, list.data(), list.size() * sizeof(uint32_t),
+                                       hipMemcpyHostToDevice, stream_));
+                HJR_TRY(hipStreamSynchronize(stream_));
+            }
+            j->lev[j->cur].live_tiles = (int64_t)list.size();
+        }
     }
     j->sched = 0;
     j->fresh = true;

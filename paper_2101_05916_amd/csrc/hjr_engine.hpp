@@ -43,7 +43,9 @@ struct Level {
     int tile_rows = 0;        // LDS tile height, 0 = default
     const void* dfield = nullptr;  // per-node disturbance boxes, or null (Job::d)
     const uint8_t* umask = nullptr; // localized update: the nodes to update, or null
-    uint8_t* tmask = nullptr;       // scratch for its per-tile flags (flat tiles)
+    uint8_t* tmask = nullptr;       // scratch for its per-tile flags
+    uint32_t* tlist = nullptr;      // scratch for the list of its plane tiles holding a node to update
+    int64_t live_tiles = -1;        // length of that list once built (plane tiles), else -1
 };
 
 // One solve job: a chain of 1..4 grid levels of one subsystem.

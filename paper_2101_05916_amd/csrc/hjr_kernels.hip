@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kStageBlock) HJR_STAGE_ATTR void k_stage(ChunkArgs 
                 if (STAGE == 2 && active) seen = __atomic_load_n(residual_word(A, cur), __ATOMIC_RELAXED);
             }
             if (!active) continue;
-            rmax = umax64(rmax, run_tile<T, STAGE, FAM>(probs[cur], states[cur], (uint32_t)(t - lo), lds));
+            rmax = umax64(rmax, run_tile<T, STAGE, FAM>(probs[cur], states[cur], (uint32_t)(t - lo), lds, rmax));
         }
     }
     if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red, seen);
@@ -544,6 +544,8 @@ static hipError_t launch_stage_t(hipStream_t s, int fam, const ChunkArgs& a, int
     case kFamX4dW2: launch_one<T, STAGE, kFamX4dW2>(s, g, b, a, e0, e1); break;
     case kFamX4dW1: launch_one<T, STAGE, kFamX4dW1>(s, g, b, a, e0, e1); break;
     case kFamXvW2: launch_one<T, STAGE, kFamXvW2>(s, g, b, a, e0, e1); break;
+    case kFamX4dMS2: launch_one<T, STAGE, kFamX4dMS2>(s, g, b, a, e0, e1); break;
+    case kFamX4dML2: launch_one<T, STAGE, kFamX4dML2>(s, g, b, a, e0, e1); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -735,6 +737,35 @@ __global__ __launch_bounds__(kBlock) void k_copy(const T* __restrict__ src, T* _
         dst[i] = src[i];
 }
 
+// Localized update on 4-D plane tiles: tmask[t] = 1 iff one node of plane
+// tile t (its rows of its plane, placed as the stage kernels place it) is
+// set in umask.  One thread per tile.
+__global__ __launch_bounds__(kBlock) void k_plane_tile_any(ProbDesc P, const uint8_t* __restrict__ umask,
+                                                           uint8_t* __restrict__ tmask)
+{
+    const int nr = P.n[2], nc = P.n[3];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < P.ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int i0, i1, chunk;
+        plane_place<4>(P, (uint32_t)t, i0, i1, chunk);
+        const int r0 = chunk * P.rows;
+        const int r1 = min(r0 + P.rows, nr);
+        const int64_t base = ((int64_t)(i0 * P.n[1] + i1) * nr + r0) * nc;
+        const int64_t cnt = (int64_t)(r1 - r0) * nc;
+        uint8_t any = 0;
+        for (int64_t e = 0; e < cnt && !any; e++) any = umask[base + e] != 0;
+        tmask[t] = any;
+    }
+}
+
+hipError_t launch_plane_tile_flags(hipStream_t s, const ProbDesc& P, const uint8_t* umask, uint8_t* tmask)
+{
+    if (P.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_plane_tile_any, dim3(grid_for(P.ntiles, 4096)), dim3(kBlock), 0, s, P, umask,
+                       tmask);
+    return hipGetLastError();
+}
+
 hipError_t launch_tile_flags(hipStream_t s, const uint8_t* umask, int64_t N, int tile,
                              uint8_t* tmask, uint64_t* count)
 {
@@ -810,6 +841,8 @@ static const void* stage_kernel(int fam)
     case kFamX4dW2: return (const void*)k_stage<T, STAGE, kFamX4dW2>;
     case kFamX4dW1: return (const void*)k_stage<T, STAGE, kFamX4dW1>;
     case kFamXvW2: return (const void*)k_stage<T, STAGE, kFamXvW2>;
+    case kFamX4dMS2: return (const void*)k_stage<T, STAGE, kFamX4dMS2>;
+    case kFamX4dML2: return (const void*)k_stage<T, STAGE, kFamX4dML2>;
     default: return (const void*)k_stage<T, STAGE, kFamXvL2F>;
     }
 }

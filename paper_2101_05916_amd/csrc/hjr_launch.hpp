@@ -43,6 +43,8 @@ hipError_t launch_field_check(hipStream_t s, int dtype, const void* f, int nch, 
 // scratch of N bytes each); a plain copy of N elements.
 hipError_t launch_tile_flags(hipStream_t s, const uint8_t* umask, int64_t N, int tile,
                              uint8_t* tmask, uint64_t* count);
+// The same per plane tile of a 4-D problem on plane tiles (P.ntiles flags).
+hipError_t launch_plane_tile_flags(hipStream_t s, const ProbDesc& P, const uint8_t* umask, uint8_t* tmask);
 hipError_t launch_band(hipStream_t s, int dtype, const hjr_grid& g, const void* V, int k,
                        uint8_t* tmp0, uint8_t* tmp1, uint8_t* node_mask);
 hipError_t launch_copy(hipStream_t s, int dtype, const void* src, void* dst, int64_t N);

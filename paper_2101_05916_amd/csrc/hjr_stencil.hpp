@@ -599,34 +599,20 @@ __device__ __forceinline__ void stage_flat(const T* in, uint32_t load0, int nc, 
 }
 
 
-// Tile t of a problem covers rows [r0, r1) of axis D-2 at a fixed index of
-// the outer axes (i0, i1 for D = 4); the host keeps (r1 - r0) * n_last <=
-// kPlaneNodesPT * kStageBlock and (r1 - r0 + 4) * RS <= plane_elems(RS).
-// The rows r0-2 .. r1+1 that exist are loaded in one batch into an LDS block with columns
-// -2 .. n_last+1 (stride RS); the missing rows and the columns past the ends
-// receive the ghost extrapolations, so every in-plane neighbour is a
-// constant LDS offset.  The outer-axis neighbours of a node (and in stage 2
-// its V and l) come straight from global memory, issued together per node.
-//
-// The node loop runs without divergent branches: a lane past the end
-// computes the tile's last node again and drops its result; only uniform
-// tests skip whole groups of 64.
-template <typename T, int D, class Ham, int STAGE, int RS, int ORDER>
-__device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
+// Plane tile `tile` of a problem -> its plane (i0, i1; 0, 0 for D = 2) and
+// chunk of rows.  4-D planes are ordered in blocks of bx consecutive axis-0
+// indices (the last block may be shorter), axis 1 next, axis 0 fastest
+// inside a block: workgroups running together then hold a compact patch of
+// (i0, i1) planes, and the neighbour planes they read were staged recently.
+template <int D, class Desc>
+__device__ __forceinline__ void plane_place(Desc& P, uint32_t tile, int& i0, int& i1, int& chunk)
 {
-    const T* __restrict__ in = (const T*)(STAGE == 1 ? P.V : P.Vhat);
-    const int ra = D - 2, ca = D - 1;  // row axis, column axis
-    const int nr = P.n[ra], nc = P.n[ca];
     const uint32_t outer = P.chunks == 1 ? tile : fdiv(tile, P.div_chunks);
-    const int chunk = (int)(tile - outer * (uint32_t)P.chunks);
-    int i0 = 0, i1 = 0;
+    chunk = (int)(tile - outer * (uint32_t)P.chunks);
+    i0 = 0;
+    i1 = 0;
     if (D == 4) {
         if (P.bx > 1) {
-            // blocked order: blocks of bx consecutive axis-0 indices (the
-            // last block may be shorter), axis 1 next, axis 0 fastest inside
-            // a block; workgroups running together then hold a compact patch
-            // of (i0, i1) planes, and the neighbour planes they read were
-            // staged recently
             const uint32_t blk = fdiv(outer, P.div_bxn1);
             const int rem = (int)(outer - blk * (uint32_t)(P.bx * P.n[1]));
             int q, bxs;
@@ -644,6 +630,34 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
             i1 = (int)outer - i0 * P.n[1];
         }
     }
+}
+
+// Tile t of a problem covers rows [r0, r1) of axis D-2 at a fixed index of
+// the outer axes (i0, i1 for D = 4); the host keeps (r1 - r0) * n_last <=
+// kPlaneNodesPT * kStageBlock and (r1 - r0 + 4) * RS <= plane_elems(RS).
+// The rows r0-2 .. r1+1 that exist are loaded in one batch into an LDS block with columns
+// -2 .. n_last+1 (stride RS); the missing rows and the columns past the ends
+// receive the ghost extrapolations, so every in-plane neighbour is a
+// constant LDS offset.  The outer-axis neighbours of a node (and in stage 2
+// its V and l) come straight from global memory, issued together per node.
+//
+// The node loop runs without divergent branches: a lane past the end
+// computes the tile's last node again and drops its result; only uniform
+// tests skip whole groups of 64.
+// MASKED (localized update, 4-D): the problem's tiles are the entries of
+// P.tlist, the plane tiles that hold a node to update, so the others cost
+// nothing and the live ones spread evenly over the XCDs; inside a tile only
+// the nodes set in P.umask are written and enter the residual (the others
+// keep V, and V-hat = V there).
+template <typename T, int D, class Ham, int STAGE, int RS, int ORDER, bool MASKED = false>
+__device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds, uint64_t rin)
+{
+    if (MASKED) tile = P.tlist[tile];
+    const T* __restrict__ in = (const T*)(STAGE == 1 ? P.V : P.Vhat);
+    const int ra = D - 2, ca = D - 1;  // row axis, column axis
+    const int nr = P.n[ra], nc = P.n[ca];
+    int i0, i1, chunk;
+    plane_place<D>(P, tile, i0, i1, chunk);
     const int r0 = chunk * P.rows;
     const int r1 = min(r0 + P.rows, nr);
     const uint32_t plane0 = (uint32_t)(i0 * P.n[1] + i1) * (uint32_t)(nr * nc);
@@ -720,7 +734,14 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
     const int edge1 = __builtin_amdgcn_readfirstlane(D == 4 && (i1 < 2 || i1 > P.n[1] - 3) ? 1 : 0);
     T* const vout = (T*)(STAGE == 1 ? P.Vhat : P.V);
     const T* const lc = (const T*)P.l;
-    uint64_t rmax = 0;
+    // the residual so far (this lane's max of |V' - V| as IEEE bits, from
+    // the workgroup's earlier tiles of the problem) and, for FP32 values,
+    // the largest float not above it: a node whose float difference is
+    // below that cannot raise the max (its exact difference is at most
+    // half an ulp above the float one), so only the others take the exact
+    // difference in double
+    uint64_t rmax = rin;
+    float rcut = __double2float_rd(__longlong_as_double((long long)rin));
     constexpr int kUnroll = STAGE == 1 ? kNodeUnroll1 : kNodeUnroll2;
     static_assert(kPlaneNodesPT * kStageBlock * kRowStrideL < (1 << 20), "fdiv20 range");
     // a lane's node k (e = lane + 64 k; lanes past the end take the tile's
@@ -732,6 +753,7 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
         T w[8];       // outer-axis samples (D = 4)
         typename Ham::Node nd;
         T vo, lv;     // stage 2: V and l at the node
+        bool upd;     // MASKED: whether the node is updated
     };
     auto load_node = [&](int k, NodeIn& N) {
         const int e = min(tid + k * kStageBlock, cnt - 1);
@@ -749,9 +771,11 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
             N.vo = gld1<T>(vout, N.vb);
             N.lv = gld1<T>(lc, N.vb);
         }
+        N.upd = true;
+        if (MASKED) N.upd = *((const HJR_GLOBAL uint8_t*)P.umask + (node0 + (uint32_t)e)) != 0;
     };
     auto compute_node = [&](int k, const NodeIn& N) {
-        const bool live = tid + k * kStageBlock < cnt;
+        const bool live = tid + k * kStageBlock < cnt && N.upd;
         const int rr = N.rr, cc = N.cc;
         const T* q = lds + __umul24((uint32_t)rr, (uint32_t)RS) + cc + (2 * RS + 2);
         const T c = q[0];
@@ -783,8 +807,16 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds)
             const T avg = T(0.5) * (N.vo + vt);
             const T vn = (N.lv < avg) ? N.lv : avg;
             if (live) gst1<T>(vn, vout, N.vb);
-            const uint64_t r = dbits(fabs((double)vn - (double)N.vo));
-            if (live && in_band(vn, N.vo, P)) rmax = umax64(rmax, r);
+            if (HJR_RES_FILTER && sizeof(T) == 4) {
+                const float d32 = fabsf((float)vn - (float)N.vo);
+                if (live && in_band(vn, N.vo, P) && !(d32 < rcut)) {
+                    rmax = umax64(rmax, dbits(fabs((double)vn - (double)N.vo)));
+                    rcut = __double2float_rd(__longlong_as_double((long long)rmax));
+                }
+            } else {
+                const uint64_t r = dbits(fabs((double)vn - (double)N.vo));
+                if (live && in_band(vn, N.vo, P)) rmax = umax64(rmax, r);
+            }
         }
     };
 #pragma unroll kUnroll
@@ -1016,7 +1048,7 @@ __device__ uint64_t tile_walk(PDesc& P, PState& S, uint32_t tile, T* lds)
 // families are fixed at compile time.
 template <typename T, int STAGE, int FAM>
 __device__ __forceinline__ uint64_t run_tile(PDesc& P, PState& S, uint32_t tile,
-                                             T* lds)
+                                             T* lds, uint64_t rin)
 {
     if constexpr (FAM == kFamFlat) {
         if (P.dfield) {
@@ -1043,16 +1075,18 @@ __device__ __forceinline__ uint64_t run_tile(PDesc& P, PState& S, uint32_t tile,
         if constexpr (fam_field(FAM)) {
             // per-node disturbance boxes
             if constexpr (M == HJR_QUAD_Z2D)
-                return tile_plane<T, 2, HamZ2DF<T>, STAGE, RS, 2>(P, S, tile, lds);
+                return tile_plane<T, 2, HamZ2DF<T>, STAGE, RS, 2>(P, S, tile, lds, rin);
             else
-                return tile_plane<T, 4, HamX4DF<T, VD>, STAGE, RS, 2>(P, S, tile, lds);
+                return tile_plane<T, 4, HamX4DF<T, VD>, STAGE, RS, 2>(P, S, tile, lds, rin);
         } else {
             if constexpr (M == HJR_QUAD_Z2D)
-                return tile_plane<T, 2, HamZ2D<T>, STAGE, RS, ORDER>(P, S, tile, lds);
+                return tile_plane<T, 2, HamZ2D<T>, STAGE, RS, ORDER>(P, S, tile, lds, rin);
             else if constexpr (fam_walk(FAM))
                 return tile_walk<T, HamX4D<T, VD>, STAGE, ORDER>(P, S, tile, lds);
+            else if constexpr (fam_masked(FAM))
+                return tile_plane<T, 4, HamX4D<T>, STAGE, RS, 2, true>(P, S, tile, lds, rin);
             else
-                return tile_plane<T, 4, HamX4D<T, VD>, STAGE, RS, ORDER>(P, S, tile, lds);
+                return tile_plane<T, 4, HamX4D<T, VD>, STAGE, RS, ORDER>(P, S, tile, lds, rin);
         }
     }
 }

@@ -123,6 +123,84 @@ def test_masked_solve_fixed_steps(case, dt):
     assert err <= (FP64_STEP_TOL if dt == "f64" else 1e-4)
 
 
+# 4-D x-subsystem masks run on the masked plane families (ENO2, constant
+# bounds): narrow and wide planes, a mask that leaves whole plane tiles
+# without a node to update (skipped), and a band update.  FP64 is held to
+# the oracle.  FP32 is held to the flat tiles' masked solve
+# (HJR_FLAG_FLAT_TILES), not to the oracle: next to the fixed nodes outside
+# a mask the masked solve is tie-prone -- on these grids the oracle itself
+# moves by 1.2e-3 .. 5.5e-3 after 25 steps when its start is perturbed by
+# one float ulp -- so FP32 rounding alone ends ~1e-3 .. 1e-2 from the FP64
+# oracle, on the flat and the plane tiles alike.
+@pytest.mark.parametrize("shape", [(9, 11, 13, 15), (5, 6, 7, 75)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_masked_plane_tiles_skip_empty_tiles(shape, dt):
+    hjr = hjr_()
+    P = W.quad_x4d(shape, 0.5)
+    rng = np.random.default_rng(11)
+    m4 = np.zeros(shape, dtype=np.uint8)
+    # nodes to update only in a slab of axis 0 and a few rows of axis 2:
+    # most plane tiles hold none
+    m4[2:4, :, 3:6, :] = (rng.random((2, shape[1], 3, shape[3])) < 0.7)
+    mask = m4.reshape(-1)
+    V0 = P.l + 0.2 * rng.standard_normal(P.size)
+    steps = 25
+    dtype = torch.float64 if dt == "f64" else torch.float32
+    V0d = dev(V0, dtype)
+    md = torch.tensor(mask, device="cuda")
+    V, st = hjr.solve_local(hjr.Spec.of(P), dev(P.l, dtype), md, V0=V0d, dtype=dtype, max_iter=steps)
+    torch.cuda.synchronize()
+    assert st["iterations"] == steps
+    if dt == "f64":
+        ref = O.solve_masked(odyn(P), ogrid(P), P.l, P.dlo, P.dhi, mask, tol=P.tol,
+                             V0=V0d.cpu().numpy(), max_iter=steps)
+        err = float(np.max(np.abs(V.cpu().numpy() - ref["V"])))
+        assert ref["iterations"] == steps
+        assert err <= FP64_STEP_TOL
+    else:
+        Vf, stf = hjr.solve_local(hjr.Spec.of(P), dev(P.l, dtype), md, V0=V0d, dtype=dtype,
+                                  max_iter=steps, flags=hjr.FLAG_FLAT_TILES)
+        torch.cuda.synchronize()
+        # (the two tile shapes evaluate in another order: measured 4.8e-7
+        # on both grids; a stencil flip would show as ~1e-3)
+        err = float((V.double() - Vf.double()).abs().max())
+        assert stf["iterations"] == steps
+        assert err <= 1e-4
+    print(f"masked plane tiles {shape} {dt}: {int(mask.sum())} of {P.size} nodes, max|dV| "
+          f"{err:.3e} against the {'oracle' if dt == 'f64' else 'flat tiles'}")
+    # nodes outside the mask keep their start, min(l, V0), bit for bit
+    st0 = np.minimum(dev(P.l, dtype).cpu().numpy(), V0d.cpu().numpy())
+    assert np.array_equal(V.cpu().numpy()[mask == 0], st0[mask == 0])
+    assert st["cell_updates"] == int(mask.sum()) * steps
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_x4d_band_update_matches_oracle(dt):
+    """The 13^4 x-subsystem converged for the bound 0.5 (oracle), updated to
+    0.55 over the band of k = 2 cells of its zero level set: 25 steps of the
+    masked plane tiles against the oracle's masked solve.  (A fixed step
+    count: the oracle's masked solve has no residual band, and over every
+    node of a 4-D band the per-step change cycles above tol.)"""
+    hjr = hjr_()
+    P5 = W.quad_x4d(13, 0.5, band=W.BAND_4D_UPDATE)
+    P = W.quad_x4d(13, 0.55)
+    old = O.solve(odyn(P5), ogrid(P5), P5.l, P5.dlo, P5.dhi, tol=P5.tol, band=P5.band)["V"]
+    dtype = torch.float64 if dt == "f64" else torch.float32
+    V0 = dev(old, dtype)
+    mask, cnt = hjr.band_mask(hjr.Spec.of(P), V0, 2)
+    m = mask.cpu().numpy()
+    steps = 25
+    ref = O.solve_masked(odyn(P), ogrid(P), P.l, P.dlo, P.dhi, m, tol=P.tol,
+                         V0=V0.cpu().numpy().astype(np.float64), max_iter=steps)
+    V, st = hjr.solve_local(hjr.Spec.of(P), dev(P.l, dtype), mask, V0=V0, dtype=dtype,
+                            max_iter=steps)
+    torch.cuda.synchronize()
+    err = float(np.max(np.abs(V.cpu().numpy().astype(np.float64) - ref["V"])))
+    print(f"x4d band update 13^4 {dt}: {steps} steps, max|dV| {err:.3e}, band {cnt} of {P.size}")
+    assert st["iterations"] == ref["iterations"] == steps
+    assert err <= (FP64_STEP_TOL if dt == "f64" else 1e-4)
+
+
 def test_empty_mask_stops_at_once():
     hjr = hjr_()
     P = W.quad_x4d(9, 0.5)
