@@ -1013,14 +1013,21 @@ def mode_precision(args, torch, hjr, W):
         with np.load(os.path.join(GOLDEN, name + ".npz"), allow_pickle=False) as z:
             G = {k: z[k] for k in z.files}
         e = {"case": label, "golden": name, "levels": [int(x) for x in G["levels"]],
-             "oracle_steps": [int(x) for x in G["level_iterations"]]}
+             "oracle_steps": [int(x) for x in G["level_iterations"]],
+             "oracle_seconds": [float(x) for x in G["level_seconds"]]}
         finals = {}
         for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
             ls = [torch.tensor(P.l, dtype=dt, device="cuda") for P in Ps]
             V0 = None if warm is None else torch.tensor(G[warm], dtype=dt, device="cuda")
-            Vs, _, _, st = hjr.solve_levels(hjr.Spec.of(Ps[-1]), [P.n for P in Ps], ls, V0=V0,
-                                            dtype=dt)
-            torch.cuda.synchronize()
+            # the second of two identical solves is timed (the first builds
+            # the engine and captures its graphs)
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                Vs, _, _, st = hjr.solve_levels(hjr.Spec.of(Ps[-1]), [P.n for P in Ps], ls, V0=V0,
+                                                dtype=dt)
+                torch.cuda.synchronize()
+                secs = time.perf_counter() - t0
             lv = []
             for k, P in enumerate(Ps):
                 V = Vs[k].double().cpu().numpy()
@@ -1035,7 +1042,7 @@ def mode_precision(args, torch, hjr, W):
                            "zero_level_disagreement": float(np.mean((V >= 0) != sign)),
                            "sampled": f"idx{k}" in G})
             finals[tag] = Vs[-1].double().cpu().numpy()
-            e[tag] = {"status": st["status"], "levels": lv}
+            e[tag] = {"status": st["status"], "seconds": secs, "levels": lv}
             del Vs, ls
             torch.cuda.empty_cache()
         e["f32_vs_f64_max_abs_diff"] = float(np.max(np.abs(finals["f32"] - finals["f64"])))
