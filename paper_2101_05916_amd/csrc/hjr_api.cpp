@@ -616,7 +616,7 @@ hjr_status hjr_solve_batch(int32_t n, const hjr_problem* probs, const hjr_opts* 
         hjr_status st = check_job_spec(&p.dyn, p.nlev, p.grids, p.d, p.tol, p.band, need_d);
         if (st != HJR_OK) return st;
         for (int k = 0; k < p.nlev; k++)
-            if (!p.l[k] || !p.V[k]) return HJR_EINVAL;
+            if (!p.l[k] || !p.V[k] || p.order[k] < 0 || p.order[k] > 2) return HJR_EINVAL;
     }
     size_t need = 0;
     hjr_status st = hjr_batch_workspace_bytes(n, probs, &op, &need);
@@ -656,6 +656,7 @@ hjr_status hjr_solve_batch(int32_t n, const hjr_problem* probs, const hjr_opts* 
                 j.lev[k].V = pr.V[k];
                 j.lev[k].mask = nullptr;
                 j.lev[k].tile_rows = pr.tile_rows[k] > 0 ? pr.tile_rows[k] : op.tile_rows;
+                j.lev[k].order = pr.order[k];
                 j.lev[k].dfield = pr.dfield[k];
                 Nmax = std::max(Nmax, grid_size(pr.grids[k]));
             }

@@ -20,6 +20,9 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #ifndef HJR_PLANE_NODES_PT
 #define HJR_PLANE_NODES_PT 8
 #endif
+#ifndef HJR_PLANE_LDS_ROWS
+#define HJR_PLANE_LDS_ROWS 18        // LDS rows of a narrow plane block (tile rows + 4)
+#endif
 #ifndef HJR_NODE_UNROLL
 #define HJR_NODE_UNROLL 2            // nodes of a lane whose loads are issued together
 #endif
@@ -79,7 +82,7 @@ constexpr int kRowStrideS = 72;      // planes whose last axis has <= 68 nodes
 constexpr int kRowStrideL = 208;     // planes whose last axis has <= 204 nodes
 constexpr int kPlaneNodesPT = HJR_PLANE_NODES_PT;   // nodes per thread of a plane tile
 constexpr int kPlaneStagePT = 2 * kPlaneNodesPT;    // staged elements per thread (register staging)
-constexpr int kPlaneElemsS = 18 * kRowStrideS;  // LDS elements of a narrow block (<= 14 rows)
+constexpr int kPlaneElemsS = HJR_PLANE_LDS_ROWS * kRowStrideS;  // LDS elements of a narrow block
 constexpr int kPlaneElemsL = 8 * kRowStrideL;   // LDS elements of a wide block (<= 4 rows)
 // Walking plane tiles: at most this many rows per tile (so the staged rows,
 // tile rows + 4 halo rows, fit the prefetch registers) and columns (a lane

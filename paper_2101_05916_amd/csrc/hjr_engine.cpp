@@ -342,7 +342,7 @@ void Engine::fill_desc(const Job* j, ProbDesc& P, int walk) const
     const hjr_grid& g = L.grid;
     P.kind = j->dyn.kind;
     P.ndim = g.ndim;
-    P.order = cfg_.order;
+    P.order = L.order > 0 ? L.order : cfg_.order;
     int64_t st = 1;
     for (int a = g.ndim - 1; a >= 0; a--) {
         P.n[a] = g.n[a];

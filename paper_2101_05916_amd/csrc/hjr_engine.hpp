@@ -41,6 +41,7 @@ struct Level {
     void* V = nullptr;
     uint8_t* mask = nullptr;  // optional refinement-mask output
     int tile_rows = 0;        // LDS tile height, 0 = default
+    int order = 0;            // derivative order of this level, 0 = EngineCfg::order
     const void* dfield = nullptr;  // per-node disturbance boxes, or null (Job::d)
     const uint8_t* umask = nullptr; // localized update: the nodes to update, or null
     uint8_t* tmask = nullptr;       // scratch for its per-tile flags

@@ -77,7 +77,8 @@ class Problem(C.Structure):
     _fields_ = [("dyn", Dyn), ("nlev", C.c_int32), ("reserved", C.c_int32),
                 ("grids", Grid * 4), ("l", C.c_void_p * 4), ("V", C.c_void_p * 4),
                 ("V0", C.c_void_p), ("d", Dstb * 2), ("tol", C.c_double),
-                ("tile_rows", C.c_int32 * 4), ("band", C.c_double), ("dfield", C.c_void_p * 4)]
+                ("tile_rows", C.c_int32 * 4), ("band", C.c_double), ("dfield", C.c_void_p * 4),
+                ("order", C.c_int32 * 4)]
 
 
 class Query(C.Structure):
@@ -507,11 +508,12 @@ def solve_levels(spec: Spec, grids_n, ls, V0=None, *, dtype=None, order=2, cfl=0
 
 
 def make_problem(spec: Spec, l, V_out, V0=None, levels=None, tile_rows=None,
-                 dtype=None, dfields=None) -> Problem:
+                 dtype=None, dfields=None, orders=None) -> Problem:
     """levels: optional list of (n, l_k, V_k) for a coarse-to-fine job; else
     one level with (spec.n, l, V_out).  tile_rows None takes the autotuned
     height of every level's shape (dtype: that of the level arrays).
-    dfields: optional per-level disturbance fields (entries may be None)."""
+    dfields: optional per-level disturbance fields (entries may be None).
+    orders: optional per-level derivative order (1, 2, or 0 = the batch's)."""
     p = Problem()
     p.dyn = make_dyn(spec.kind, spec.params)
     if levels is None:
@@ -541,6 +543,8 @@ def make_problem(spec: Spec, l, V_out, V0=None, levels=None, tile_rows=None,
             n, lk, _ = levels[k]
             _check_field(f, spec.kind, int(np.prod(n)), lk.dtype, f"dfields[{k}]")
             p.dfield[k] = f.data_ptr()
+    for k, o in enumerate(orders or []):
+        p.order[k] = int(o)
     return p
 
 

@@ -43,9 +43,9 @@ int main(void){
    sizeof(hjr_dstb), sizeof(hjr_opts), sizeof(hjr_stats), sizeof(hjr_problem),
    sizeof(hjr_server_cfg), sizeof(hjr_request), sizeof(hjr_reply), sizeof(hjr_query),
    sizeof(hjr_subsystem), sizeof(hjr_query_decomposed));
- printf("%zu %zu %zu %zu %zu %zu\n", offsetof(hjr_opts, flags),
+ printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(hjr_opts, flags),
    offsetof(hjr_stats, kernel_launches), offsetof(hjr_problem, tol), offsetof(hjr_request, cold),
-   offsetof(hjr_problem, dfield), offsetof(hjr_request, dfield));
+   offsetof(hjr_problem, dfield), offsetof(hjr_request, dfield), offsetof(hjr_problem, order));
  return 0; }
 """
     with tempfile.TemporaryDirectory() as d:
@@ -60,7 +60,8 @@ int main(void){
             C.sizeof(hjr.Request), C.sizeof(hjr.Reply), C.sizeof(hjr.Query),
             C.sizeof(hjr.Subsystem), C.sizeof(hjr.QueryDecomposed),
             hjr.Opts.flags.offset, hjr.Stats.kernel_launches.offset, hjr.Problem.tol.offset,
-            hjr.Request.cold.offset, hjr.Problem.dfield.offset, hjr.Request.dfield.offset]
+            hjr.Request.cold.offset, hjr.Problem.dfield.offset, hjr.Request.dfield.offset,
+            hjr.Problem.order.offset]
     assert got == want
 
 
@@ -147,6 +148,24 @@ def test_solve_rejects_invalid_arguments_without_device(what):
     r = L.hjr_solve(C.byref(dyn), C.byref(g), lptr, None, d, tol, C.byref(_opts(**kw)),
                     C.c_void_p(0x2000), C.byref(it), C.byref(res))
     assert r == hjr.EINVAL
+
+
+@pytest.mark.parametrize("order", [-1, 3])
+def test_batch_rejects_invalid_level_order_without_device(order):
+    """A per-level derivative order outside 0..2 is EINVAL before any HIP call."""
+    L = hjr.lib()
+    p = hjr.Problem()
+    p.dyn = hjr.make_dyn(hjr.QUAD_Z2D, (0.91, 9.81, 7.0, 16.0))
+    p.nlev = 2
+    for k in range(2):
+        p.grids[k] = hjr.make_grid([51, 51], [0.0, -4.0], [3.0, 4.0])
+        p.l[k] = 0x1000  # never dereferenced: validation fails first
+        p.V[k] = 0x2000
+    dd = hjr.make_dstb([-0.5], [0.5])
+    p.d[0] = dd[0]
+    p.tol = 1e-4
+    p.order[1] = order
+    assert L.hjr_solve_batch(1, C.byref(p), C.byref(_opts()), None) == hjr.EINVAL
 
 
 def test_interp_and_mask_reject_invalid():

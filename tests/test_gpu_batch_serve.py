@@ -186,6 +186,32 @@ def test_batch_multilevel_jobs_equal_single_levels():
         assert st["level_iterations"] == st1["level_iterations"]
 
 
+@pytest.mark.parametrize("pair", ["x4d", "z2d"])
+def test_batch_per_level_order_matches_oracle(pair):
+    """A chain whose coarse level runs the first-order scheme and whose fine
+    level runs ENO2 (Sec. II-C), in FP64: each level against the oracle run
+    with that level's order, started the same way (the coarse level cold, the
+    fine level from the multilinear interpolation of the coarse result)."""
+    hjr = hjr_()
+    Pc, Pf = ((W.quad_x4d(11, 0.5), W.quad_x4d(17, 0.5)) if pair == "x4d"
+              else (W.quad_z2d(51, 0.4), W.quad_z2d(101, 0.4)))
+    lc, lf = dev(Pc.l, torch.float64), dev(Pf.l, torch.float64)
+    Vc, Vf = torch.empty_like(lc), torch.empty_like(lf)
+    prob = hjr.make_problem(hjr.Spec.of(Pf), None, None,
+                            levels=[(Pc.n, lc, Vc), (Pf.n, lf, Vf)], orders=[1, 2])
+    r, stats = hjr.solve_batch([prob], max_iter=20000)
+    torch.cuda.synchronize()
+    rc = oracle_solve(Pc, order=1)
+    V0 = O.interp(O.make_grid(Pc.n, Pc.lo, Pc.hi), rc["V"], O.make_grid(Pf.n, Pf.lo, Pf.hi))
+    rf = oracle_solve(Pf, V0=V0, order=2)
+    assert stats[0]["level_iterations"][:2] == [rc["iterations"], rf["iterations"]]
+    assert np.max(np.abs(Vc.cpu().numpy() - rc["V"])) <= 1e-9
+    assert np.max(np.abs(Vf.cpu().numpy() - rf["V"])) <= 5e-5  # the FP64 parity bar
+    # the coarse level is the plain order-1 solve, bit for bit
+    V1, st1 = single(Pc, dtype=torch.float64, order=1)
+    assert torch.equal(V1, Vc) and st1["iterations"] == rc["iterations"]
+
+
 def test_graph_replays_stable():
     """Captured chunk graphs are reused across calls (engine pool); replays
     interleaved with eager work give identical results every time."""
