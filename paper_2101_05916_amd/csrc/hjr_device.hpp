@@ -43,7 +43,7 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
                                      // allows, measured 17-20 % slower)
 #endif
 #ifndef HJR_PLANE_BLOCK
-#define HJR_PLANE_BLOCK 4            // 4-D plane tiles: axis-0 indices per block of the plane order
+#define HJR_PLANE_BLOCK 8            // 4-D plane tiles: axis-0 indices per block of the plane order
 #endif
 #ifndef HJR_TILES_PER_WG_MAX
 #define HJR_TILES_PER_WG_MAX 16      // more tiles per workgroup of the capped grid: a workgroup per
