@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--count", type=int, default=256, help="batch mode: problems")
     ap.add_argument("--requests", type=int, default=3000, help="serve mode: requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve mode: req/s")
+    ap.add_argument("--hbm-budget-mib", type=int, default=8192,
+                    help="serve mode: device-memory budget of the server (MiB)")
     return ap.parse_args()
 
 
@@ -873,7 +875,7 @@ def mode_serve(args, torch, hjr, W):
              else W.quad_z2d(I["n"]))
         specs[I["instance"]] = P
         ls[I["instance"]] = P.l.astype(np.float32)
-    srv = hjr.Server(hbm_budget_bytes=8 << 30, max_active=64, chunk=args.chunk or 16)
+    srv = hjr.Server(hbm_budget_bytes=args.hbm_budget_mib << 20, max_active=64, chunk=args.chunk or 16)
     seen = set()
     tickets = []
     t0 = time.perf_counter()
@@ -904,6 +906,8 @@ def mode_serve(args, torch, hjr, W):
         "metric": "safe-set updates/s and p50/p99 latency (served)", "mode": "serve",
         "requests": len(replies), "converged": ok, "rate_offered": args.rate,
         "updates_per_s": len(replies) / wall, "cell_updates_per_s": cu / wall,
+        # the load the stream asks for: the offered rate times the mean work per request
+        "offered_cell_updates_per_s": args.rate * cu / len(replies),
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": float(np.mean(lat))},
         "warm_fraction": float(np.mean([rep["warm"] for rep in warm])),
         "hbm_used_bytes": used, "hbm_budget_bytes": budget, "dtype": "f32", "data": "synthetic",
