@@ -24,7 +24,13 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #define HJR_PLANE_LDS_ROWS 18        // LDS rows of a narrow plane block (tile rows + 4)
 #endif
 #ifndef HJR_NODE_UNROLL
-#define HJR_NODE_UNROLL 2            // nodes of a lane whose loads are issued together
+#define HJR_NODE_UNROLL 2            // plain node loop (no pipeline): nodes per unrolled iteration
+#endif
+#ifndef HJR_NODE_PIPE
+#define HJR_NODE_PIPE 3              // FP32 plane tiles, bit s-1 for stage s: request a node's operands before computing the previous one
+#endif
+#ifndef HJR_NODE_PIPE_UNROLL
+#define HJR_NODE_PIPE_UNROLL 1
 #endif
 #ifndef HJR_BLOCKS_PER_CU
 #define HJR_BLOCKS_PER_CU 20         // cap on stage workgroups per CU (5 single-wave groups per SIMD)

@@ -819,12 +819,36 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds, uint6
             }
         }
     };
+    if constexpr (sizeof(T) == 4 && ((HJR_NODE_PIPE >> (STAGE - 1)) & 1) != 0) {
+        // Software pipeline (FP32): node k + 1's global operands are
+        // requested before node k is computed, so a wave keeps two nodes'
+        // loads in flight.  The loads are unconditional (a lane past the
+        // end, or a group past the last, loads the tile's last node), so the
+        // wait before each compute only covers the older node's loads.  The
+        // second set of operands costs registers (stage 2: 89 VGPRs, five
+        // waves per SIMD instead of seven) and still wins; in FP64 it loses
+        // (twice the registers per operand).
+        NodeIn Na, Nb;
+        load_node(0, Na);
+#if HJR_NODE_PIPE_UNROLL
+#pragma unroll
+#endif
+        for (int k = 0; k < kPlaneNodesPT; k += 2) {
+            load_node(k + 1, Nb);
+            compute_node(k, Na);
+            if ((k + 1) * kStageBlock >= cnt) break;
+            load_node(k + 2, Na);
+            compute_node(k + 1, Nb);
+            if ((k + 2) * kStageBlock >= cnt) break;
+        }
+    } else {
 #pragma unroll kUnroll
-    for (int k = 0; k < kPlaneNodesPT; k++) {
-        if (k * kStageBlock < cnt) {
-            NodeIn N;
-            load_node(k, N);
-            compute_node(k, N);
+        for (int k = 0; k < kPlaneNodesPT; k++) {
+            if (k * kStageBlock < cnt) {
+                NodeIn N;
+                load_node(k, N);
+                compute_node(k, N);
+            }
         }
     }
     __syncthreads();  // the LDS block is reused by the next tile
