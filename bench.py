@@ -268,8 +268,8 @@ def mode_mix(args, torch, hjr, W):
         "hbm_frac_end_to_end": value * 24.0 / (HBM_PEAK_GBS * 1e9),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_stage<float,2,3> (4-D narrow-plane ENO2 family: RK stage 2 + projection + "
-                      "residual), "
+            "kernel": "k_stage<float,2,3,true> (4-D narrow-plane ENO2 family, the deep-pipelined "
+                      "kernel of runs of tiles: RK stage 2 + projection + residual), "
                       f"the mix's {n4} 4-D problems batched ({n4nodes} nodes, all live)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -418,8 +418,8 @@ def mode_step(args, torch, hjr, W):
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_stage<float,2,3> (4-D narrow-plane ENO2 family: RK stage 2 + projection + "
-                      "residual), "
+            "kernel": "k_stage<float,2,3,false> (4-D narrow-plane ENO2 family: RK stage 2 + "
+                      "projection + residual), "
                       "x,y 41^4 batched",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -29,8 +29,17 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #ifndef HJR_NODE_PIPE
 #define HJR_NODE_PIPE 3              // FP32 plane tiles, bit s-1 for stage s: request a node's operands before computing the previous one
 #endif
-#ifndef HJR_NODE_PIPE_UNROLL
-#define HJR_NODE_PIPE_UNROLL 1
+#ifndef HJR_NODE_PIPE_DEPTH1
+#define HJR_NODE_PIPE_DEPTH1 1       // nodes requested ahead of the one computed, stage 1
+#endif
+#ifndef HJR_NODE_PIPE_DEPTH2
+#define HJR_NODE_PIPE_DEPTH2 1       // and stage 2
+#endif
+#ifndef HJR_NODE_PIPE_DEEP1
+#define HJR_NODE_PIPE_DEEP1 3        // the same in the deep kernels of large tile sets, stage 1
+#endif
+#ifndef HJR_NODE_PIPE_DEEP2
+#define HJR_NODE_PIPE_DEEP2 2        // and stage 2
 #endif
 #ifndef HJR_BLOCKS_PER_CU
 #define HJR_BLOCKS_PER_CU 20         // cap on stage workgroups per CU (5 single-wave groups per SIMD)
@@ -125,6 +134,14 @@ __host__ __device__ constexpr bool fam_masked(int f)
 __host__ __device__ constexpr bool fam_walk(int f)
 {
     return f >= kFamX4dW2 && f <= kFamXvW2;
+}
+
+// Families with a second, deeper-pipelined FP32 stage kernel for launches
+// whose workgroups take runs of tiles (the 4-D plane families with constant
+// disturbance boxes).
+__host__ __device__ constexpr bool fam_deep(int f)
+{
+    return f == kFamX4dS2 || f == kFamX4dL2 || f == kFamXvS2 || f == kFamXvL2;
 }
 
 // Model of a plane family (HJR_QUAD_Z2D, HJR_QUAD_X4D, HJR_QUAD_X4DV; -1 flat).

@@ -634,7 +634,7 @@ hjr_status Engine::enqueue_stage(int stage, const ChunkArgs& a, bool fork, hipEv
         for (int i = 0; i < n; i++) {
             const Launch& l = launches_[i];
             HJR_TRY(launch_stage(stream_, cfg_.dtype, stage, l.fam, a, l.grid[stage - 1],
-                                 i == 0 ? e0 : nullptr, i == n - 1 ? e1 : nullptr));
+                                 i == 0 ? e0 : nullptr, i == n - 1 ? e1 : nullptr, l.deep[stage - 1]));
         }
         return HJR_OK;
     }
@@ -642,10 +642,12 @@ hjr_status Engine::enqueue_stage(int stage, const ChunkArgs& a, bool fork, hipEv
     for (int i = 1; i < n; i++) {
         const Launch& l = launches_[i];
         HJR_TRY(hipStreamWaitEvent(side_[l.fam], fork_ev_, 0));
-        HJR_TRY(launch_stage(side_[l.fam], cfg_.dtype, stage, l.fam, a, l.grid[stage - 1]));
+        HJR_TRY(launch_stage(side_[l.fam], cfg_.dtype, stage, l.fam, a, l.grid[stage - 1], nullptr,
+                             nullptr, l.deep[stage - 1]));
         HJR_TRY(hipEventRecord(join_ev_[l.fam], side_[l.fam]));
     }
-    HJR_TRY(launch_stage(stream_, cfg_.dtype, stage, launches_[0].fam, a, launches_[0].grid[stage - 1]));
+    HJR_TRY(launch_stage(stream_, cfg_.dtype, stage, launches_[0].fam, a, launches_[0].grid[stage - 1],
+                         nullptr, nullptr, launches_[0].deep[stage - 1]));
     for (int i = 1; i < n; i++) HJR_TRY(hipStreamWaitEvent(stream_, join_ev_[launches_[i].fam], 0));
     return HJR_OK;
 }
@@ -762,6 +764,7 @@ hjr_status Engine::step()
                 cap = (int)std::min<int64_t>(INT32_MAX / 16, (per_xcd + run - 1) / run) * 8;
             }
             hdr->fam_run[st][fm] = run;
+            l.deep[st] = run > 1;
             l.grid[st] = (int)std::min<int64_t>(cap, std::max<int64_t>(8, (nt + 7) / 8 * 8));
         }
         launches_.push_back(l);

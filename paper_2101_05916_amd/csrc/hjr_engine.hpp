@@ -171,9 +171,11 @@ private:
     struct Launch {
         int fam;
         int grid[2];
+        bool deep[2] = {false, false};  // per stage: runs of tiles, deeper-pipelined kernel
         bool operator==(const Launch& o) const
         {
-            return fam == o.fam && grid[0] == o.grid[0] && grid[1] == o.grid[1];
+            return fam == o.fam && grid[0] == o.grid[0] && grid[1] == o.grid[1] &&
+                   deep[0] == o.deep[0] && deep[1] == o.deep[1];
         }
     };
 

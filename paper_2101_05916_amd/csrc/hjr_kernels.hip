@@ -133,7 +133,7 @@ __device__ __forceinline__ void flush_residual(const ChunkArgs& A, int p, uint64
 // into eight contiguous ranges, one per XCD (workgroup b runs on XCD b mod
 // 8), and the workgroups of an XCD stride through its range (one tile each
 // when the grid has a workgroup per tile).
-template <typename T, int STAGE, int FAM>
+template <typename T, int STAGE, int FAM, bool DEEP = false>
 __global__ __launch_bounds__(kStageBlock) HJR_STAGE_ATTR void k_stage(ChunkArgs A)
 {
     // a plane block (and a spare slot per lane for staging through registers)
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kStageBlock) HJR_STAGE_ATTR void k_stage(ChunkArgs 
                 if (STAGE == 2 && active) seen = __atomic_load_n(residual_word(A, cur), __ATOMIC_RELAXED);
             }
             if (!active) continue;
-            rmax = umax64(rmax, run_tile<T, STAGE, FAM>(probs[cur], states[cur], (uint32_t)(t - lo), lds, rmax));
+            rmax = umax64(rmax, run_tile<T, STAGE, FAM, DEEP>(probs[cur], states[cur], (uint32_t)(t - lo), lds, rmax));
         }
     }
     if (STAGE == 2 && cur >= 0 && active) flush_residual<kStageBlock>(A, cur, rmax, red, seen);
@@ -509,56 +509,71 @@ hipError_t launch_epilogue(hipStream_t s, const ChunkArgs& a)
 // One stage kernel.  With events (the timed chunks of HJR_FLAG_PROFILE) the
 // runtime stamps them at the kernel's own start and end, so the measured
 // time holds no gap between launches.
-template <typename T, int STAGE, int FAM>
-static void launch_one(hipStream_t s, dim3 g, dim3 b, const ChunkArgs& a, hipEvent_t e0, hipEvent_t e1)
+template <typename T, int STAGE, int FAM, bool DEEP>
+static void launch_kernel(hipStream_t s, dim3 g, dim3 b, const ChunkArgs& a, hipEvent_t e0, hipEvent_t e1)
 {
     if (e0 || e1)
-        hipExtLaunchKernelGGL((k_stage<T, STAGE, FAM>), g, b, 0, s, e0, e1, 0, a);
+        hipExtLaunchKernelGGL((k_stage<T, STAGE, FAM, DEEP>), g, b, 0, s, e0, e1, 0, a);
     else
-        hipLaunchKernelGGL((k_stage<T, STAGE, FAM>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_stage<T, STAGE, FAM, DEEP>), g, b, 0, s, a);
+}
+
+// deep: the launch's workgroups take runs of tiles (a large set); the
+// families that have one then run their deeper-pipelined FP32 kernel.
+template <typename T, int STAGE, int FAM>
+static void launch_one(hipStream_t s, dim3 g, dim3 b, const ChunkArgs& a, hipEvent_t e0, hipEvent_t e1,
+                       bool deep)
+{
+    if constexpr (sizeof(T) == 4 && fam_deep(FAM)) {
+        if (deep) {
+            launch_kernel<T, STAGE, FAM, true>(s, g, b, a, e0, e1);
+            return;
+        }
+    }
+    launch_kernel<T, STAGE, FAM, false>(s, g, b, a, e0, e1);
 }
 
 template <typename T, int STAGE>
 static hipError_t launch_stage_t(hipStream_t s, int fam, const ChunkArgs& a, int grid, hipEvent_t e0,
-                                 hipEvent_t e1)
+                                 hipEvent_t e1, bool deep)
 {
     const dim3 g(grid), b(kStageBlock);
     switch (fam) {
-    case kFamFlat: launch_one<T, STAGE, kFamFlat>(s, g, b, a, e0, e1); break;
-    case kFamZ2dS2: launch_one<T, STAGE, kFamZ2dS2>(s, g, b, a, e0, e1); break;
-    case kFamZ2dL2: launch_one<T, STAGE, kFamZ2dL2>(s, g, b, a, e0, e1); break;
-    case kFamX4dS2: launch_one<T, STAGE, kFamX4dS2>(s, g, b, a, e0, e1); break;
-    case kFamX4dL2: launch_one<T, STAGE, kFamX4dL2>(s, g, b, a, e0, e1); break;
-    case kFamZ2dS1: launch_one<T, STAGE, kFamZ2dS1>(s, g, b, a, e0, e1); break;
-    case kFamZ2dL1: launch_one<T, STAGE, kFamZ2dL1>(s, g, b, a, e0, e1); break;
-    case kFamX4dS1: launch_one<T, STAGE, kFamX4dS1>(s, g, b, a, e0, e1); break;
-    case kFamX4dL1: launch_one<T, STAGE, kFamX4dL1>(s, g, b, a, e0, e1); break;
-    case kFamZ2dS2F: launch_one<T, STAGE, kFamZ2dS2F>(s, g, b, a, e0, e1); break;
-    case kFamZ2dL2F: launch_one<T, STAGE, kFamZ2dL2F>(s, g, b, a, e0, e1); break;
-    case kFamX4dS2F: launch_one<T, STAGE, kFamX4dS2F>(s, g, b, a, e0, e1); break;
-    case kFamX4dL2F: launch_one<T, STAGE, kFamX4dL2F>(s, g, b, a, e0, e1); break;
-    case kFamXvS2: launch_one<T, STAGE, kFamXvS2>(s, g, b, a, e0, e1); break;
-    case kFamXvL2: launch_one<T, STAGE, kFamXvL2>(s, g, b, a, e0, e1); break;
-    case kFamXvS2F: launch_one<T, STAGE, kFamXvS2F>(s, g, b, a, e0, e1); break;
-    case kFamXvL2F: launch_one<T, STAGE, kFamXvL2F>(s, g, b, a, e0, e1); break;
-    case kFamX4dW2: launch_one<T, STAGE, kFamX4dW2>(s, g, b, a, e0, e1); break;
-    case kFamX4dW1: launch_one<T, STAGE, kFamX4dW1>(s, g, b, a, e0, e1); break;
-    case kFamXvW2: launch_one<T, STAGE, kFamXvW2>(s, g, b, a, e0, e1); break;
-    case kFamX4dMS2: launch_one<T, STAGE, kFamX4dMS2>(s, g, b, a, e0, e1); break;
-    case kFamX4dML2: launch_one<T, STAGE, kFamX4dML2>(s, g, b, a, e0, e1); break;
+    case kFamFlat: launch_one<T, STAGE, kFamFlat>(s, g, b, a, e0, e1, deep); break;
+    case kFamZ2dS2: launch_one<T, STAGE, kFamZ2dS2>(s, g, b, a, e0, e1, deep); break;
+    case kFamZ2dL2: launch_one<T, STAGE, kFamZ2dL2>(s, g, b, a, e0, e1, deep); break;
+    case kFamX4dS2: launch_one<T, STAGE, kFamX4dS2>(s, g, b, a, e0, e1, deep); break;
+    case kFamX4dL2: launch_one<T, STAGE, kFamX4dL2>(s, g, b, a, e0, e1, deep); break;
+    case kFamZ2dS1: launch_one<T, STAGE, kFamZ2dS1>(s, g, b, a, e0, e1, deep); break;
+    case kFamZ2dL1: launch_one<T, STAGE, kFamZ2dL1>(s, g, b, a, e0, e1, deep); break;
+    case kFamX4dS1: launch_one<T, STAGE, kFamX4dS1>(s, g, b, a, e0, e1, deep); break;
+    case kFamX4dL1: launch_one<T, STAGE, kFamX4dL1>(s, g, b, a, e0, e1, deep); break;
+    case kFamZ2dS2F: launch_one<T, STAGE, kFamZ2dS2F>(s, g, b, a, e0, e1, deep); break;
+    case kFamZ2dL2F: launch_one<T, STAGE, kFamZ2dL2F>(s, g, b, a, e0, e1, deep); break;
+    case kFamX4dS2F: launch_one<T, STAGE, kFamX4dS2F>(s, g, b, a, e0, e1, deep); break;
+    case kFamX4dL2F: launch_one<T, STAGE, kFamX4dL2F>(s, g, b, a, e0, e1, deep); break;
+    case kFamXvS2: launch_one<T, STAGE, kFamXvS2>(s, g, b, a, e0, e1, deep); break;
+    case kFamXvL2: launch_one<T, STAGE, kFamXvL2>(s, g, b, a, e0, e1, deep); break;
+    case kFamXvS2F: launch_one<T, STAGE, kFamXvS2F>(s, g, b, a, e0, e1, deep); break;
+    case kFamXvL2F: launch_one<T, STAGE, kFamXvL2F>(s, g, b, a, e0, e1, deep); break;
+    case kFamX4dW2: launch_one<T, STAGE, kFamX4dW2>(s, g, b, a, e0, e1, deep); break;
+    case kFamX4dW1: launch_one<T, STAGE, kFamX4dW1>(s, g, b, a, e0, e1, deep); break;
+    case kFamXvW2: launch_one<T, STAGE, kFamXvW2>(s, g, b, a, e0, e1, deep); break;
+    case kFamX4dMS2: launch_one<T, STAGE, kFamX4dMS2>(s, g, b, a, e0, e1, deep); break;
+    case kFamX4dML2: launch_one<T, STAGE, kFamX4dML2>(s, g, b, a, e0, e1, deep); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_stage(hipStream_t s, int dtype, int stage, int fam, const ChunkArgs& a, int grid,
-                        hipEvent_t e0, hipEvent_t e1)
+                        hipEvent_t e0, hipEvent_t e1, bool deep)
 {
     if (dtype == HJR_F32)
-        return stage == 1 ? launch_stage_t<float, 1>(s, fam, a, grid, e0, e1)
-                          : launch_stage_t<float, 2>(s, fam, a, grid, e0, e1);
-    return stage == 1 ? launch_stage_t<double, 1>(s, fam, a, grid, e0, e1)
-                      : launch_stage_t<double, 2>(s, fam, a, grid, e0, e1);
+        return stage == 1 ? launch_stage_t<float, 1>(s, fam, a, grid, e0, e1, deep)
+                          : launch_stage_t<float, 2>(s, fam, a, grid, e0, e1, deep);
+    return stage == 1 ? launch_stage_t<double, 1>(s, fam, a, grid, e0, e1, deep)
+                      : launch_stage_t<double, 2>(s, fam, a, grid, e0, e1, deep);
 }
 
 hipError_t launch_level_setup(hipStream_t s, int dtype, const ProbDesc& P, ProbState* st)

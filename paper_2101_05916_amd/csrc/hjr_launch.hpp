@@ -11,9 +11,11 @@ namespace hjr {
 // Iteration kernels (one chunk = prologue, K x (stage 1, stage 2), epilogue).
 hipError_t launch_prologue(hipStream_t s, const ChunkArgs& a);
 // One RK stage over the tiles of family fam (see Family).
-// e0 / e1, when given, are stamped at the kernel's start / end.
+// e0 / e1, when given, are stamped at the kernel's start / end.  deep: the
+// workgroups take runs of tiles (a large set), so the family's deeper-
+// pipelined FP32 kernel runs where it has one.
 hipError_t launch_stage(hipStream_t s, int dtype, int stage, int fam, const ChunkArgs& a, int grid,
-                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, bool deep = false);
 hipError_t launch_epilogue(hipStream_t s, const ChunkArgs& a);
 
 // Per-level set-up of one problem: Lax-Friedrichs bounds, time step and

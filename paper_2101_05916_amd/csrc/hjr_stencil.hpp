@@ -649,7 +649,7 @@ __device__ __forceinline__ void plane_place(Desc& P, uint32_t tile, int& i0, int
 // nothing and the live ones spread evenly over the XCDs; inside a tile only
 // the nodes set in P.umask are written and enter the residual (the others
 // keep V, and V-hat = V there).
-template <typename T, int D, class Ham, int STAGE, int RS, int ORDER, bool MASKED = false>
+template <typename T, int D, class Ham, int STAGE, int RS, int ORDER, bool MASKED = false, bool DEEP = false>
 __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds, uint64_t rin)
 {
     if (MASKED) tile = P.tlist[tile];
@@ -820,26 +820,28 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds, uint6
         }
     };
     if constexpr (sizeof(T) == 4 && ((HJR_NODE_PIPE >> (STAGE - 1)) & 1) != 0) {
-        // Software pipeline (FP32): node k + 1's global operands are
-        // requested before node k is computed, so a wave keeps two nodes'
-        // loads in flight.  The loads are unconditional (a lane past the
-        // end, or a group past the last, loads the tile's last node), so the
-        // wait before each compute only covers the older node's loads.  The
-        // second set of operands costs registers (stage 2: 89 VGPRs, five
-        // waves per SIMD instead of seven) and still wins; in FP64 it loses
-        // (twice the registers per operand).
-        NodeIn Na, Nb;
-        load_node(0, Na);
-#if HJR_NODE_PIPE_UNROLL
+        // Software pipeline (FP32): the global operands of the next kDepth
+        // nodes of a lane are requested before a node is computed, so a
+        // wave keeps several nodes' loads in flight.  The loads are
+        // unconditional (a lane past the end, or a group past the last,
+        // loads the tile's last node), so the wait before each compute only
+        // covers the oldest node's loads.  The extra operand sets cost
+        // registers (stage 2 at depth 1: 89 VGPRs, five waves per SIMD
+        // instead of seven) and still win; in FP64 (twice the registers per
+        // operand) the pipeline loses.  DEEP kernels (large tile sets, run
+        // by workgroups taking runs of tiles) request further ahead: they
+        // trade more waves for more loads in flight per wave, which pays
+        // there and not on small sets.
+        constexpr int kDepth = DEEP ? (STAGE == 1 ? HJR_NODE_PIPE_DEEP1 : HJR_NODE_PIPE_DEEP2)
+                                    : (STAGE == 1 ? HJR_NODE_PIPE_DEPTH1 : HJR_NODE_PIPE_DEPTH2);
+        NodeIn Nq[kDepth + 1];
 #pragma unroll
-#endif
-        for (int k = 0; k < kPlaneNodesPT; k += 2) {
-            load_node(k + 1, Nb);
-            compute_node(k, Na);
-            if ((k + 1) * kStageBlock >= cnt) break;
-            load_node(k + 2, Na);
-            compute_node(k + 1, Nb);
-            if ((k + 2) * kStageBlock >= cnt) break;
+        for (int d = 0; d < kDepth; d++) load_node(d, Nq[d]);
+#pragma unroll
+        for (int k = 0; k < kPlaneNodesPT; k++) {
+            if (k * kStageBlock >= cnt) break;
+            load_node(k + kDepth, Nq[(k + kDepth) % (kDepth + 1)]);
+            compute_node(k, Nq[k % (kDepth + 1)]);
         }
     } else {
 #pragma unroll kUnroll
@@ -1070,7 +1072,7 @@ __device__ uint64_t tile_walk(PDesc& P, PState& S, uint32_t tile, T* lds)
 // One tile of a family (see Family): flat tiles dispatch on the model (and
 // on whether the problem has a disturbance field) at run time, plane
 // families are fixed at compile time.
-template <typename T, int STAGE, int FAM>
+template <typename T, int STAGE, int FAM, bool DEEP = false>
 __device__ __forceinline__ uint64_t run_tile(PDesc& P, PState& S, uint32_t tile,
                                              T* lds, uint64_t rin)
 {
@@ -1110,7 +1112,7 @@ __device__ __forceinline__ uint64_t run_tile(PDesc& P, PState& S, uint32_t tile,
             else if constexpr (fam_masked(FAM))
                 return tile_plane<T, 4, HamX4D<T>, STAGE, RS, 2, true>(P, S, tile, lds, rin);
             else
-                return tile_plane<T, 4, HamX4D<T, VD>, STAGE, RS, ORDER>(P, S, tile, lds, rin);
+                return tile_plane<T, 4, HamX4D<T, VD>, STAGE, RS, ORDER, false, DEEP>(P, S, tile, lds, rin);
         }
     }
 }
