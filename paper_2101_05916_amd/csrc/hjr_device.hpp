@@ -36,10 +36,10 @@ constexpr int kBlock = 256;          // threads per workgroup of the utility ker
 #define HJR_NODE_PIPE_DEPTH2 1       // and stage 2
 #endif
 #ifndef HJR_NODE_PIPE_DEEP1
-#define HJR_NODE_PIPE_DEEP1 3        // the same in the deep kernels of large tile sets, stage 1
+#define HJR_NODE_PIPE_DEEP1 5        // the same in the deep kernels of large tile sets, stage 1
 #endif
 #ifndef HJR_NODE_PIPE_DEEP2
-#define HJR_NODE_PIPE_DEEP2 2        // and stage 2
+#define HJR_NODE_PIPE_DEEP2 3        // and stage 2
 #endif
 #ifndef HJR_BLOCKS_PER_CU
 #define HJR_BLOCKS_PER_CU 20         // cap on stage workgroups per CU (5 single-wave groups per SIMD)
