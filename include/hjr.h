@@ -326,11 +326,12 @@ typedef struct hjr_problem {
     const void* dfield[4];  /* per level: per-node disturbance boxes (device,
                                layout of hjr_solve_field), or NULL = the
                                constant boxes d (then d must be valid) */
-    int32_t order[4];       /* per level: spatial derivative order (Sec. II-C:
-                               1 = one-sided first order, 2 = ENO2), 0 =
-                               hjr_opts.order; any other value is EINVAL.  A
-                               coarse level may take order 1 for a cheaper
-                               start of the finer level's ENO2 solve. */
+    int32_t order[4];       /* per level: spatial derivative order (1 =
+                               one-sided first order, 2 = ENO2), 0 =
+                               hjr_opts.order; any other value is EINVAL.
+                               Sec. III-C: a coarse level with cheap gradient
+                               approximations (order 1) starts the finer
+                               level's ENO2 solve. */
 } hjr_problem;
 
 /* Bytes of device workspace hjr_solve_batch needs for these problems. */

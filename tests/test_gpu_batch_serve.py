@@ -189,7 +189,8 @@ def test_batch_multilevel_jobs_equal_single_levels():
 @pytest.mark.parametrize("pair", ["x4d", "z2d"])
 def test_batch_per_level_order_matches_oracle(pair):
     """A chain whose coarse level runs the first-order scheme and whose fine
-    level runs ENO2 (Sec. II-C), in FP64: each level against the oracle run
+    level runs ENO2 (Sec. III-C: cheap gradient approximations on the coarse
+    grid), in FP64: each level against the oracle run
     with that level's order, started the same way (the coarse level cold, the
     fine level from the multilinear interpolation of the coarse result)."""
     hjr = hjr_()
