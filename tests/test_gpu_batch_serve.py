@@ -186,6 +186,25 @@ def test_batch_multilevel_jobs_equal_single_levels():
         assert st["level_iterations"] == st1["level_iterations"]
 
 
+def test_batch_large_set_runs_of_tiles_bit_identical():
+    """Four 61^4 problems batched hold more plane tiles than 16 per workgroup
+    of a capped grid, so the launch gives each workgroup a run of tiles and
+    takes the deeper-pipelined FP32 kernels; one 61^4 problem alone runs the
+    capped grid.  The arithmetic per node is the same: every result equals
+    its single solve bit for bit (30 steps from the cold start)."""
+    hjr = hjr_()
+    Ps = [W.quad_x4d(61, d, f"p{i}") for i, d in enumerate((0.3, 0.5, 0.7, 0.9))]
+    ls = [dev(P.l) for P in Ps]
+    Vs = [torch.empty_like(l) for l in ls]
+    probs = [hjr.make_problem(hjr.Spec.of(P), l, V) for P, l, V in zip(Ps, ls, Vs)]
+    r, stats = hjr.solve_batch(probs, max_iter=30)
+    torch.cuda.synchronize()
+    for P, l, V, st in zip(Ps, ls, Vs, stats):
+        V1, st1 = single(P, max_iter=30)
+        assert st["iterations"] == st1["iterations"] == 30
+        assert torch.equal(V, V1)
+
+
 @pytest.mark.parametrize("pair", ["x4d", "z2d"])
 def test_batch_per_level_order_matches_oracle(pair):
     """A chain whose coarse level runs the first-order scheme and whose fine
