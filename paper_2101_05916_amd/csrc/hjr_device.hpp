@@ -99,6 +99,11 @@ constexpr int kPlaneNodesPT = HJR_PLANE_NODES_PT;   // nodes per thread of a pla
 constexpr int kPlaneStagePT = 2 * kPlaneNodesPT;    // staged elements per thread (register staging)
 constexpr int kPlaneElemsS = HJR_PLANE_LDS_ROWS * kRowStrideS;  // LDS elements of a narrow block
 constexpr int kPlaneElemsL = 8 * kRowStrideL;   // LDS elements of a wide block (<= 4 rows)
+// LDS elements after a plane block for its row records (coefficient, index) of up to 16 rows
+constexpr int kRowRecElems = 32;
+static_assert(kPlaneElemsS / kRowStrideS - 4 <= kRowRecElems / 2 &&
+                  kPlaneElemsL / kRowStrideL - 4 <= kRowRecElems / 2,
+              "row records cover every tile row");
 // Walking plane tiles: at most this many rows per tile (so the staged rows,
 // tile rows + 4 halo rows, fit the prefetch registers) and columns (a lane
 // per column).

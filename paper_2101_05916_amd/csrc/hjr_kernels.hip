@@ -136,9 +136,11 @@ __device__ __forceinline__ void flush_residual(const ChunkArgs& A, int p, uint64
 template <typename T, int STAGE, int FAM, bool DEEP = false>
 __global__ __launch_bounds__(kStageBlock) HJR_STAGE_ATTR void k_stage(ChunkArgs A)
 {
-    // a plane block (and a spare slot per lane for staging through registers)
+    // a plane block (and a spare slot per lane for staging through registers),
+    // then the tile's row records
     constexpr int kElems = FAM == kFamFlat ? 4
-                                           : plane_elems(fam_rs(FAM)) + (stage_by_dma(STAGE) ? 0 : kStageBlock);
+                                           : plane_elems(fam_rs(FAM)) + (stage_by_dma(STAGE) ? 0 : kStageBlock) +
+                                                 kRowRecElems;
     __shared__ uint64_t red[kStageBlock / 64];
     __shared__ __align__(16) char smem[kElems * sizeof(T)];
     T* lds = (T*)smem;

@@ -176,6 +176,7 @@ __device__ __forceinline__ void ghost_fix(int j, int n, T c, T& m2, T& m1, T& p1
 // Cpos = (max(k u) + min(d) - g) hih1, Cneg = (min(k u) + max(d) - g) hih1.
 template <typename T>
 struct HamZ2D {
+    static constexpr bool kRowRecords = false;
     T c0, c1, cpos, cneg;
     __device__ void init(PDesc& P)
     {
@@ -206,6 +207,7 @@ struct HamZ2D {
 // - g) hih1, hc[6] = hih1.
 template <typename T>
 struct HamZ2DF {
+    static constexpr bool kRowRecords = false;
     T c0, c1, kpos, kneg, h1;
     const T* flo;
     const T* fhi;
@@ -247,6 +249,8 @@ struct HamZ2DF {
 // (x' = vx, vx' = g tan(theta) + d); then hc[2], hc[3] = dlo*hih1, dhi*hih1.
 template <typename T, bool VD = false>
 struct HamX4D {
+    // plane tiles keep each tile row's coefficient and index (as T) in LDS
+    static constexpr bool kRowRecords = true;
     T c0, c1, dl, dh, A, B, C, D, E, n0s;
     const T* gts;
     __device__ void init(PDesc& P)
@@ -291,6 +295,11 @@ struct HamX4D {
     {
         return eval_terms(sum, coef_vx(j1), coef_tw(j2, j3), coef_t3(j2), g);
     }
+    // the same with the row index already converted (j2f == (T)j2, exact)
+    __device__ __forceinline__ T eval_f(const T* sum, int j1, T j2f, int j3, T g) const
+    {
+        return eval_terms(sum, coef_vx(j1), A + (T)j3 * B - j2f * C, D + j2f * E, g);
+    }
     __device__ __forceinline__ T operator()(const T* sum, int j0, int j1, int j2, int j3) const
     {
         return eval(sum, j0, j1, j2, j3, row_coef(j2));
@@ -305,6 +314,7 @@ struct HamX4D {
 // HamZ2DF) on x', hc[10] = hih0, or with VD on vx', hc[10] = hih1.
 template <typename T, bool VD = false>
 struct HamX4DF {
+    static constexpr bool kRowRecords = false;
     T c0, c1, h0, A, B, C, D, E, n0s;
     const T* gts;
     const T* flo;
@@ -688,6 +698,16 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds, uint6
         stage_dma<T, RS>(in, load0, nc, lr1 - lr0, lrow, lds, tid);
     else
         stage_flat<T, RS>(in, load0, nc, lr1 - lr0, lrow, lds, tid, P.div_last);
+    // row records past the block: each tile row's Hamiltonian coefficient
+    // and its index as T, read by the nodes from LDS instead of a global
+    // load, an add, a shift and a conversion per node
+    T* const rowrec = lds + plane_elems(RS) + (stage_by_dma(STAGE) ? 0 : kStageBlock);
+    if constexpr (D == 4 && Ham::kRowRecords) {
+        if (tid < r1 - r0) {
+            rowrec[2 * tid] = ld32((const T*)P.table, (uint32_t)(r0 + tid));
+            rowrec[2 * tid + 1] = (T)(r0 + tid);
+        }
+    }
     __syncthreads();
     const int nghc = (lr1 - lr0) * 4;
     for (int e = tid; e < nghc; e += kStageBlock) {
@@ -752,6 +772,7 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds, uint6
         int rr, cc;   // its row and column in the tile
         T w[8];       // outer-axis samples (D = 4)
         typename Ham::Node nd;
+        T j2f;        // row records: the node's row index as T
         T vo, lv;     // stage 2: V and l at the node
         bool upd;     // MASKED: whether the node is updated
     };
@@ -765,7 +786,13 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds, uint6
             for (int qq = 0; qq < 8; qq++) N.w[qq] = gld1<T>(nb[qq], N.vb);
         }
         // per-node Hamiltonian data (row coefficient, disturbance box)
-        N.nd = ham.node_b(r0 + N.rr, N.vb);
+        if constexpr (D == 4 && Ham::kRowRecords) {
+            N.nd = rowrec[2 * N.rr];
+            N.j2f = rowrec[2 * N.rr + 1];
+        } else {
+            N.nd = ham.node_b(r0 + N.rr, N.vb);
+            N.j2f = T(0);
+        }
         N.vo = N.lv = T(0);
         if (STAGE == 2) {
             N.vo = gld1<T>(vout, N.vb);
@@ -796,7 +823,10 @@ __device__ uint64_t tile_plane(PDesc& P, PState& S, uint32_t tile, T* lds, uint6
             if (edge1) ghost_fix<T>(i1, P.n[1], c, m2, m1, p1, p2);
             eno_sd<T, ORDER>(m2, m1, c, p1, p2, sum[1], dif);
             L += ah[1] * dif;
-            L += ham.eval(sum, i0, i1, r0 + rr, cc, N.nd);
+            if constexpr (Ham::kRowRecords)
+                L += ham.eval_f(sum, i1, N.j2f, cc, N.nd);
+            else
+                L += ham.eval(sum, i0, i1, r0 + rr, cc, N.nd);
         } else {
             L += ham.eval(sum, r0 + rr, cc, 0, 0, N.nd);
         }
